@@ -62,8 +62,13 @@ CASE_NODES = {
 }
 CASE_KIND = {0: PTK, 1: PE, 2: PE, 3: PE, 4: PP, 5: PP, 6: PP, 7: EEK, 8: PE, 9: PE,
              10: PE, 11: PE, 12: PP, 13: PP, 14: PP, 15: PP}
-PARALLEL_EPS = 1e-20   # ||e1 x e2||^2 < eps ||e1||^2 ||e2||^2 => parallel edges
+PARALLEL_EPS = 1e-12   # ||e1 x e2||^2 < eps ||e1||^2 ||e2||^2 => parallel edges (sin < 1e-6)
 CCD_EPS = 1e-12        # root interval [-eps, 1+eps] and activation d_TOC < eps + dhat
+
+
+def _dz_sign(v):
+    """Sign with a dead zone of the CCD epsilon (reading: |sd| <= eps counts as touching)."""
+    return 0 if abs(v) <= CCD_EPS else (1 if v > 0 else -1)
 
 
 def _dot(a, b):
@@ -117,7 +122,8 @@ def classify_ee(A0, A1, B0, B1):
     a, b, c = _dot(e1, e1), _dot(e1, e2), _dot(e2, e2)
     d, e = _dot(e1, w), _dot(e2, w)
     parallel = nn < PARALLEL_EPS * a * c
-    den = np.where(parallel, 1.0, a * c - b * b)
+    # a c - b^2 = |e1 x e2|^2 (Lagrange identity); the cross-product form has no cancellation
+    den = np.where(parallel, 1.0, nn)
     s = (b * e - c * d) / den
     t = (a * e - b * d) / den
     interior = (~parallel) & (s >= 0) & (s <= 1) & (t >= 0) & (t <= 1)
@@ -664,9 +670,14 @@ class OracleScene:
         root whose distance d_TOC < eps + dhat is activated, tau = t_{i+1};
         for point-triangle / edge-edge interior cases tau shrinks by 0.9
         while sign sd(tau) != sign sd((t_i + tau) / 2) (reading of the
-        reference-frame rule); point-point / point-edge cases keep tau.
+        reference-frame rule; |sd| <= eps counts as sign 0, so a tau sitting
+        on the coplanarity root always backs off); point-point / point-edge
+        cases keep tau.
         Edge pairs parallel at both ends of the step are skipped (reading: a
-        parallel edge pair is coplanar for every t).
+        parallel edge pair is coplanar for every t), and roots at t <= eps
+        are not activated (reading: they describe the feasible start of the
+        step; activating them would pin alpha_max at 0 once an iterate lands
+        on a point-edge time of coplanarity).
         """
         K = len(pairs)
         tau = np.ones(K)
@@ -699,7 +710,8 @@ class OracleScene:
         t_prev = np.zeros(K)
         for k in range(3):
             r = roots[:, k]
-            cand = np.isfinite(r) & ~done
+            # a root at t <= eps describes the (feasible) start of the step: not activated (reading)
+            cand = np.isfinite(r) & ~done & (r > CCD_EPS)
             if not cand.any():
                 continue
             idx = np.nonzero(cand)[0]
@@ -719,7 +731,7 @@ class OracleScene:
                     for _ in range(400):
                         s1 = self._signed_dist(kd, (X0[i] + t_i * P[i])[None])[0]
                         s0 = self._signed_dist(kd, (X0[i] + 0.5 * (tp[j] + t_i) * P[i])[None])[0]
-                        if np.sign(s1) == np.sign(s0):
+                        if _dz_sign(s1) == _dz_sign(s0):
                             break
                         t_i *= 0.9
                 tau[i] = t_i
@@ -820,6 +832,8 @@ class OracleScene:
                 x = xn
                 converged = True
                 break
+            if alpha == 0.0 and len(st.aug) == 0:
+                break  # no step and nothing left to update: stalled (reading)
             # dual and penalty updates (Alg. 1, lines 12-17)
             dn, _ = self.distances(xn, swept)
             if len(st.aug):
