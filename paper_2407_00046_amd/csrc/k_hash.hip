@@ -1,0 +1,364 @@
+// Spatial-hash candidate pass (supporting kernel; replaces the paper's two
+// LBVHs of Sec. 5.3 broad phase).
+//
+// Entry primitives (triangles for point-triangle, edges for edge-edge) are
+// inserted into every grid cell their dhat-inflated box (optionally swept
+// over [x, x + p]) overlaps; cells hash into a bucket table built by a
+// counting sort.  Each query primitive (surface vertex, surface edge) scans
+// the cells of its own box; a pair is reported only in the lowest cell of
+// the overlap of the two cell ranges, so it is found once.  Primitives
+// whose box spans more than kLargeCells cells (big obstacle faces) are kept
+// out of the grid and tested directly.  Queries count first, then write at
+// scanned offsets and sort their own segment, so the final list is in
+// canonical (kind, a, b) order with no global sort and no atomics in the
+// output.
+#include "bal_internal.h"
+
+namespace bal {
+
+constexpr int kHB = 256;
+constexpr long kLargeCells = 64;
+constexpr long kQueryCells = 4096;
+constexpr int kOff = 1 << 20;
+
+struct Box { double lo[3], hi[3]; };
+
+__device__ __forceinline__ uint64_t cell_key(int ix, int iy, int iz) {
+  return ((uint64_t)(ix + kOff) << 42) | ((uint64_t)(iy + kOff) << 21) | (uint64_t)(iz + kOff);
+}
+__device__ __forceinline__ uint32_t hash64(uint64_t k, uint32_t mask) {
+  k ^= k >> 33;
+  k *= 0xff51afd7ed558ccdULL;
+  k ^= k >> 33;
+  k *= 0xc4ceb9fe1a85ec53ULL;
+  k ^= k >> 33;
+  return (uint32_t)k & mask;
+}
+// Cell coordinate, clamped so that the integer conversion is always defined.
+__device__ __forceinline__ int cellc(double v, double ih) {
+  double c = floor(v * ih);
+  c = c > (double)(kOff - 2) ? (double)(kOff - 2) : (c < -(double)(kOff - 2) ? -(double)(kOff - 2) : c);
+  return (int)c;
+}
+// Number of grid cells a box spans (a huge value for non-finite boxes).
+__device__ __forceinline__ double box_cells(const double *lo, const double *hi, double ih) {
+  double n = 1.0;
+  for (int c = 0; c < 3; ++c) {
+    if (!(lo[c] <= hi[c]) || !isfinite(lo[c]) || !isfinite(hi[c])) return 1e300;
+    n *= floor(hi[c] * ih) - floor(lo[c] * ih) + 1.0;
+  }
+  return n;
+}
+
+// primitive types: 0 vertex (sv), 1 triangle (st), 2 edge (se)
+__device__ __forceinline__ int prim_verts(int type, int i, const int *sv, const int *st, const int *se, int *v) {
+  if (type == 0) { v[0] = sv[i]; return 1; }
+  if (type == 1) { v[0] = st[3 * i]; v[1] = st[3 * i + 1]; v[2] = st[3 * i + 2]; return 3; }
+  v[0] = se[2 * i]; v[1] = se[2 * i + 1]; return 2;
+}
+
+__device__ Box prim_box(int type, int i, const int *sv, const int *st, const int *se, const double *x,
+                        const double *p, double infl) {
+  int v[3];
+  int nv = prim_verts(type, i, sv, st, se, v);
+  Box b;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) { b.lo[c] = INFINITY; b.hi[c] = -INFINITY; }
+  for (int k = 0; k < nv; ++k)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      double a = x[3 * v[k] + c];
+      double e = p ? a + p[3 * v[k] + c] : a;
+      double lo = a < e ? a : e, hi = a < e ? e : a;
+      b.lo[c] = lo < b.lo[c] ? lo : b.lo[c];
+      b.hi[c] = hi > b.hi[c] ? hi : b.hi[c];
+    }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) { b.lo[c] -= infl; b.hi[c] += infl; }
+  return b;
+}
+
+// Entry boxes (inflated), cell counts, large flags.
+__global__ void k_entry_boxes(int n, int type, const int *sv, const int *st, const int *se, const double *x,
+                              const double *p, double infl, double ih, Box *boxes, int *cnt, int *large_list,
+                              int *nlarge) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  Box b = prim_box(type, i, sv, st, se, x, p, infl);
+  boxes[i] = b;
+  double nc = box_cells(b.lo, b.hi, ih);
+  if (nc > (double)kLargeCells) {
+    cnt[i] = 0;
+    int k = atomicAdd(nlarge, 1);
+    large_list[k] = i;
+  } else {
+    cnt[i] = (int)nc;
+  }
+}
+
+__global__ void k_entry_write(int n, const Box *boxes, const int *cnt, const int *off, double ih, uint32_t mask,
+                              uint64_t *ekey, int *eprim, int *bcnt) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || cnt[i] == 0) return;
+  Box b = boxes[i];
+  int l[3], h[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) { l[c] = cellc(b.lo[c], ih); h[c] = cellc(b.hi[c], ih); }
+  int o = off[i];
+  for (int ix = l[0]; ix <= h[0]; ++ix)
+    for (int iy = l[1]; iy <= h[1]; ++iy)
+      for (int iz = l[2]; iz <= h[2]; ++iz) {
+        uint64_t k = cell_key(ix, iy, iz);
+        ekey[o] = k;
+        eprim[o] = i;
+        atomicAdd(&bcnt[hash64(k, mask)], 1);
+        ++o;
+      }
+}
+
+__global__ void k_entry_scatter(int E, const uint64_t *ekey, const int *eprim, uint32_t mask, const int *bstart,
+                                int *bfill, uint64_t *skey, int *sprim) {
+  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= E) return;
+  uint32_t b = hash64(ekey[e], mask);
+  int pos = bstart[b] + atomicAdd(&bfill[b], 1);
+  skey[pos] = ekey[e];
+  sprim[pos] = eprim[e];
+}
+
+struct QueryArgs {
+  int qtype, etype, nq, ne;
+  const int *sv, *st, *se;
+  const uint8_t *fr;
+  int nbody;
+  const double *x, *p;
+  const Box *ebox;
+  double ih;
+  uint32_t mask;
+  const int *bstart;
+  const uint64_t *skey;
+  const int *sprim;
+  const int *large_list;
+  int nlarge;
+  const uint8_t *qlarge;  // EE: query edge is large (brute-force role)
+};
+
+__device__ __forceinline__ bool boxes_overlap(const Box &a, const Box &b) {
+  return a.lo[0] <= b.hi[0] && b.lo[0] <= a.hi[0] && a.lo[1] <= b.hi[1] && b.lo[1] <= a.hi[1] &&
+         a.lo[2] <= b.hi[2] && b.lo[2] <= a.hi[2];
+}
+
+// Pair filters (reading): no shared vertex, not obstacle-only, some free node.
+__device__ bool pair_ok(const QueryArgs &A, int q, int t) {
+  int vq[3], vt[3];
+  int nq = prim_verts(A.qtype, q, A.sv, A.st, A.se, vq);
+  int nt = prim_verts(A.etype, t, A.sv, A.st, A.se, vt);
+  bool anyfree = false;
+  for (int a = 0; a < nq; ++a) {
+    anyfree |= A.fr[vq[a]] != 0;
+    for (int b = 0; b < nt; ++b)
+      if (vq[a] == vt[b]) return false;
+  }
+  for (int b = 0; b < nt; ++b) anyfree |= A.fr[vt[b]] != 0;
+  if (!anyfree) return false;
+  bool qobs = vq[0] >= A.nbody, tobs = vt[0] >= A.nbody;
+  return !(qobs && tobs);
+}
+
+// Visits the candidate partners of query q; emit(t) for each.  For edge-edge
+// only partners t > q are reported (each unordered pair once, in the segment
+// of its smaller edge).
+template <typename F>
+__device__ void visit_query(const QueryArgs &A, int q, F emit) {
+  Box qb = prim_box(A.qtype, q, A.sv, A.st, A.se, A.x, A.p, 0.0);
+  bool ee = A.qtype == 2;
+  if ((ee && A.qlarge[q]) || box_cells(qb.lo, qb.hi, A.ih) > (double)kQueryCells) {
+    // large query (big obstacle edge, or a box spanning too many cells):
+    // direct test against every entry (every later edge for edge-edge)
+    for (int t = ee ? q + 1 : 0; t < A.ne; ++t)
+      if (boxes_overlap(qb, A.ebox[t]) && pair_ok(A, q, t)) emit(t);
+    return;
+  }
+  int l[3], h[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) { l[c] = cellc(qb.lo[c], A.ih); h[c] = cellc(qb.hi[c], A.ih); }
+  for (int ix = l[0]; ix <= h[0]; ++ix)
+    for (int iy = l[1]; iy <= h[1]; ++iy)
+      for (int iz = l[2]; iz <= h[2]; ++iz) {
+        uint64_t k = cell_key(ix, iy, iz);
+        uint32_t b = hash64(k, A.mask);
+        for (int e = A.bstart[b]; e < A.bstart[b + 1]; ++e) {
+          if (A.skey[e] != k) continue;
+          int t = A.sprim[e];
+          if (ee && t <= q) continue;
+          const Box &tb = A.ebox[t];
+          // canonical cell: lowest cell of the overlap of the two cell ranges
+          int c0 = max(l[0], cellc(tb.lo[0], A.ih)), c1 = max(l[1], cellc(tb.lo[1], A.ih)),
+              c2 = max(l[2], cellc(tb.lo[2], A.ih));
+          if (c0 != ix || c1 != iy || c2 != iz) continue;
+          if (boxes_overlap(qb, tb) && pair_ok(A, q, t)) emit(t);
+        }
+      }
+  for (int k = 0; k < A.nlarge; ++k) {
+    int t = A.large_list[k];
+    if (ee && t <= q) continue;
+    if (boxes_overlap(qb, A.ebox[t]) && pair_ok(A, q, t)) emit(t);
+  }
+}
+
+__global__ void k_query_count(QueryArgs A, int *qcnt) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= A.nq) return;
+  int c = 0;
+  visit_query(A, q, [&](int) { ++c; });
+  qcnt[q] = c;
+}
+
+__global__ void k_query_write(QueryArgs A, const int *qoff, int *outb) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= A.nq) return;
+  int o = qoff[q];
+  visit_query(A, q, [&](int t) { outb[o++] = t; });
+  // insertion sort of the segment (canonical order)
+  int lo = qoff[q];
+  for (int a = lo + 1; a < o; ++a) {
+    int v = outb[a], b = a - 1;
+    while (b >= lo && outb[b] > v) { outb[b + 1] = outb[b]; --b; }
+    outb[b + 1] = v;
+  }
+}
+
+__global__ void k_large_flag(int n, const Box *ebox, double ih, uint8_t *fl) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  Box b = ebox[i];
+  fl[i] = box_cells(b.lo, b.hi, ih) > (double)kLargeCells ? 1 : 0;
+}
+
+__global__ void k_emit_pairs(int nq, int kind, const int *qoff, const int *outb, const int *sv, const int *st,
+                             const int *se, int base, int *okind, int *oa, int *ob, int4 *onodes, uint64_t *okey) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nq) return;
+  for (int k = qoff[q]; k < qoff[q + 1]; ++k) {
+    int t = outb[k];
+    int o = base + k;
+    okind[o] = kind;
+    oa[o] = q;
+    ob[o] = t;
+    int4 nd;
+    if (kind == 0) nd = make_int4(sv[q], st[3 * t], st[3 * t + 1], st[3 * t + 2]);
+    else nd = make_int4(se[2 * q], se[2 * q + 1], se[2 * t], se[2 * t + 1]);
+    onodes[o] = nd;
+    okey[o] = ((uint64_t)kind << 62) | ((uint64_t)q << 31) | (uint64_t)t;
+  }
+}
+
+static int grow_pairs(PairList &pl, int n) {
+  size_t m = (size_t)(n > 0 ? n : 1);
+  if (pl.kind.grow(m * sizeof(int)) || pl.a.grow(m * sizeof(int)) || pl.b.grow(m * sizeof(int)) ||
+      pl.nodes.grow(m * sizeof(int4)) || pl.d.grow(m * sizeof(double)) || pl.cs.grow(m * sizeof(int)) ||
+      pl.key.grow(m * sizeof(uint64_t)))
+    return BAL_E_OOM;
+  return BAL_OK;
+}
+
+// One half of the pass (point-triangle or edge-edge); returns the pair count
+// (negative on error) and leaves per-query offsets / partner lists in the
+// scene's scratch (h_qoff, h_out) for k_emit_pairs.
+static int hash_half(Scene &s, int qtype, int etype, const double *x, const double *p, int *qoff_out_n,
+                     DBuf &qoff_buf, DBuf &out_buf) {
+  int nq = qtype == 0 ? s.nsv : s.nse;
+  int ne = etype == 1 ? s.nst : s.nse;
+  double ih = 1.0 / s.cell;
+  double infl = s.desc.dhat;
+  if (s.hb_lo.grow((size_t)(ne + 1) * sizeof(Box)) || s.h_cnt.grow((size_t)(ne + 1) * sizeof(int)) ||
+      s.h_off.grow((size_t)(ne + 1) * sizeof(int)) || s.h_large.grow((size_t)(ne + 1) * sizeof(int)) ||
+      s.h_nlarge.grow(2 * sizeof(int)) || s.hq_lo.grow((size_t)(nq + 1) * sizeof(uint8_t)))
+    return BAL_E_OOM;
+  Box *ebox = s.hb_lo.as<Box>();
+  int *nlarge_d = s.h_nlarge.as<int>();
+  hipMemsetAsync(nlarge_d, 0, sizeof(int), s.stream);
+  if (ne > 0)
+    hipLaunchKernelGGL(k_entry_boxes, dim3(blocks_for(ne, kHB)), dim3(kHB), 0, s.stream, ne, etype, s.sv.as<int>(),
+                       s.st.as<int>(), s.se.as<int>(), x, p, infl, ih, ebox, s.h_cnt.as<int>(), s.h_large.as<int>(),
+                       nlarge_d);
+  int E = scan_exclusive(s, s.h_cnt.as<int>(), s.h_off.as<int>(), ne);
+  int *hn = s.pin.as<int>();
+  hipMemcpyAsync(hn, nlarge_d, sizeof(int), hipMemcpyDeviceToHost, s.stream);
+  hipStreamSynchronize(s.stream);
+  int nlarge = hn[0];
+  uint32_t M = 1024;
+  while ((long)M < 2L * E) M <<= 1;
+  if (s.h_key.grow((size_t)(E + 1) * sizeof(uint64_t)) || s.h_prim.grow((size_t)(E + 1) * sizeof(int)) ||
+      s.h_skey.grow((size_t)(E + 1) * sizeof(uint64_t)) || s.h_sprim.grow((size_t)(E + 1) * sizeof(int)) ||
+      s.h_bcnt.grow((size_t)(M + 1) * sizeof(int)) || s.h_bstart.grow((size_t)(M + 1) * sizeof(int)) ||
+      s.h_bfill.grow((size_t)(M + 1) * sizeof(int)))
+    return BAL_E_OOM;
+  hipMemsetAsync(s.h_bcnt.p, 0, (M + 1) * sizeof(int), s.stream);
+  hipMemsetAsync(s.h_bfill.p, 0, (M + 1) * sizeof(int), s.stream);
+  if (ne > 0)
+    hipLaunchKernelGGL(k_entry_write, dim3(blocks_for(ne, kHB)), dim3(kHB), 0, s.stream, ne, ebox, s.h_cnt.as<int>(),
+                       s.h_off.as<int>(), ih, M - 1, s.h_key.as<uint64_t>(), s.h_prim.as<int>(), s.h_bcnt.as<int>());
+  scan_exclusive(s, s.h_bcnt.as<int>(), s.h_bstart.as<int>(), (int)M + 1);
+  if (E > 0)
+    hipLaunchKernelGGL(k_entry_scatter, dim3(blocks_for(E, kHB)), dim3(kHB), 0, s.stream, E, s.h_key.as<uint64_t>(),
+                       s.h_prim.as<int>(), M - 1, s.h_bstart.as<int>(), s.h_bfill.as<int>(), s.h_skey.as<uint64_t>(),
+                       s.h_sprim.as<int>());
+  uint8_t *qlarge = s.hq_lo.as<uint8_t>();
+  if (qtype == 2 && ne > 0)
+    hipLaunchKernelGGL(k_large_flag, dim3(blocks_for(ne, kHB)), dim3(kHB), 0, s.stream, ne, ebox, ih, qlarge);
+  QueryArgs A;
+  A.qtype = qtype; A.etype = etype; A.nq = nq; A.ne = ne;
+  A.sv = s.sv.as<int>(); A.st = s.st.as<int>(); A.se = s.se.as<int>();
+  A.fr = s.freev.as<uint8_t>(); A.nbody = s.nb; A.x = x; A.p = p; A.ebox = ebox; A.ih = ih; A.mask = M - 1;
+  A.bstart = s.h_bstart.as<int>(); A.skey = s.h_skey.as<uint64_t>(); A.sprim = s.h_sprim.as<int>();
+  A.large_list = s.h_large.as<int>(); A.nlarge = nlarge; A.qlarge = qlarge;
+  if (s.h_qcnt.grow((size_t)(nq + 1) * sizeof(int)) || qoff_buf.grow((size_t)(nq + 1) * sizeof(int))) return BAL_E_OOM;
+  hipMemsetAsync(s.h_qcnt.p, 0, (nq + 1) * sizeof(int), s.stream);
+  if (nq > 0) hipLaunchKernelGGL(k_query_count, dim3(blocks_for(nq, 128)), dim3(128), 0, s.stream, A, s.h_qcnt.as<int>());
+  int P = scan_exclusive(s, s.h_qcnt.as<int>(), qoff_buf.as<int>(), nq + 1);
+  if (out_buf.grow((size_t)(P + 1) * sizeof(int))) return BAL_E_OOM;
+  if (nq > 0 && P > 0)
+    hipLaunchKernelGGL(k_query_write, dim3(blocks_for(nq, 128)), dim3(128), 0, s.stream, A, qoff_buf.as<int>(),
+                       out_buf.as<int>());
+  *qoff_out_n = nq;
+  return P;
+}
+
+int build_candidates(Scene &s, PairList &out, const double *x, const double *p) {
+  out.n = 0;
+  if (s.nsv == 0 && s.nse == 0) return BAL_OK;
+  DBuf &qoff_pt = s.qoff_pt, &out_pt = s.out_pt;
+  int nq_pt = 0, nq_ee = 0;
+  int Ppt = hash_half(s, 0, 1, x, p, &nq_pt, qoff_pt, out_pt);
+  if (Ppt < 0) return Ppt;
+  // emit PT pairs before the EE pass reuses the scratch
+  if (grow_pairs(out, Ppt)) return BAL_E_OOM;
+  if (nq_pt > 0 && Ppt > 0)
+    hipLaunchKernelGGL(k_emit_pairs, dim3(blocks_for(nq_pt, kHB)), dim3(kHB), 0, s.stream, nq_pt, 0,
+                       qoff_pt.as<int>(), out_pt.as<int>(), s.sv.as<int>(), s.st.as<int>(), s.se.as<int>(), 0,
+                       out.kind.as<int>(), out.a.as<int>(), out.b.as<int>(), out.nodes.as<int4>(),
+                       out.key.as<uint64_t>());
+  hipStreamSynchronize(s.stream);
+  DBuf &qoff_ee = s.qoff_ee, &out_ee = s.out_ee;
+  int Pee = hash_half(s, 2, 2, x, p, &nq_ee, qoff_ee, out_ee);
+  if (Pee < 0) return Pee;
+  int total = Ppt + Pee;
+  if (Pee > 0) {
+    // grow keeps nothing: re-emit the PT half after growing
+    if (grow_pairs(out, total)) return BAL_E_OOM;
+    if (nq_pt > 0 && Ppt > 0)
+      hipLaunchKernelGGL(k_emit_pairs, dim3(blocks_for(nq_pt, kHB)), dim3(kHB), 0, s.stream, nq_pt, 0,
+                         qoff_pt.as<int>(), out_pt.as<int>(), s.sv.as<int>(), s.st.as<int>(), s.se.as<int>(), 0,
+                         out.kind.as<int>(), out.a.as<int>(), out.b.as<int>(), out.nodes.as<int4>(),
+                         out.key.as<uint64_t>());
+    hipLaunchKernelGGL(k_emit_pairs, dim3(blocks_for(nq_ee, kHB)), dim3(kHB), 0, s.stream, nq_ee, 1,
+                       qoff_ee.as<int>(), out_ee.as<int>(), s.sv.as<int>(), s.st.as<int>(), s.se.as<int>(), Ppt,
+                       out.kind.as<int>(), out.a.as<int>(), out.b.as<int>(), out.nodes.as<int4>(),
+                       out.key.as<uint64_t>());
+  }
+  out.n = total;
+  return BAL_OK;
+}
+
+}  // namespace bal

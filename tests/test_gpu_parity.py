@@ -1,0 +1,199 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle.
+
+Kernel-level checks evaluate both sides at the same iterate and state;
+step-level checks run both through whole time steps.  Tolerances:
+FP64 kernels 1e-9 relative (rounding of different but exact algorithms),
+FP64 trajectories 1e-6 of the bounding-box diagonal, mixed precision 1e-4.
+"""
+import numpy as np
+import pytest
+
+import scenes
+from oracle import ALState, OracleScene, Pairs, Params
+
+pytestmark = pytest.mark.gpu
+
+
+def lib_scene(sc, **kw):
+    from paper_2407_00046_amd import Scene
+    return Scene(sc, **kw)
+
+
+def contact_state(sc, depth=4e-4, seed=7, every=3):
+    """Cube pressed to `depth` above the plane with a hand-made augmentation set."""
+    o = OracleScene(sc)
+    x = o.x.copy()
+    x[: o.n_body, 1] -= x[: o.n_body, 1].min() - depth
+    rng = np.random.default_rng(seed)
+    x[: o.n_body] += rng.uniform(-2e-5, 2e-5, size=(o.n_body, 3))
+    pairs = o.all_pairs()
+    d, _ = o.distances(x, pairs)
+    act = np.nonzero(d < o.dhat)[0]
+    aug = pairs.take(act[::every])
+    st = ALState(sigma=3e4, sigma0=3e4, aug=aug, mu=rng.uniform(0, 50, len(aug)), s=rng.uniform(0, 2e-4, len(aug)))
+    y = o.predictor(o.x, o.v)
+    return o, x, y, pairs, st
+
+
+def map_aug(g, aug: Pairs):
+    """Oracle pairs -> (kind, library primitive ids)."""
+    sv, st, se = g.surface()
+    vpos = {int(v): i for i, v in enumerate(sv)}
+    tpos = {tuple(sorted(map(int, t))): i for i, t in enumerate(st)}
+    epos = {tuple(sorted(map(int, e))): i for i, e in enumerate(se)}
+    kind = aug.kind.astype(np.int32)
+    prims = np.zeros((len(aug), 2), np.int32)
+    for j in range(len(aug)):
+        nd = aug.nodes[j]
+        if aug.kind[j] == 0:
+            prims[j] = (vpos[int(nd[0])], tpos[tuple(sorted(map(int, nd[1:])))])
+        else:
+            prims[j] = (epos[tuple(sorted(map(int, nd[:2])))], epos[tuple(sorted(map(int, nd[2:])))])
+    return kind, prims
+
+
+def free_rows(o, a):
+    return a[o.free_idx].reshape(-1)
+
+
+@pytest.fixture(scope="module")
+def contact_case():
+    sc = scenes.tiny_cube()
+    o, x, y, pairs, st = contact_state(sc)
+    return sc, o, x, y, pairs, st
+
+
+@pytest.mark.parametrize("project", [True, False])
+def test_linearize_energy_gradient_hessian(contact_case, project):
+    sc, o, x, y, pairs, st = contact_case
+    g = lib_scene(sc)
+    kind, prims = map_aug(g, st.aug)
+    E, grad, nact = g.linearize(x, st.sigma, kind, prims, st.mu, st.s, project=project)
+    L, gref = o.lagrangian(x, y, pairs, st, with_grad=True)
+    d, _ = o.distances(x, pairs)
+    print(f"pairs active {nact} (oracle {(d < o.dhat).sum()}), |A'| = {len(st.aug)}, E = {E:.12e} vs {L:.12e}")
+    assert nact == int((d < o.dhat).sum())
+    assert abs(E - L) <= 1e-10 * abs(L)
+    gf, rf = free_rows(o, grad), free_rows(o, gref)
+    assert np.abs(gf - rf).max() <= 1e-9 * np.abs(rf).max()
+    H = o.hessian(x, pairs, st, project=project)
+    rng = np.random.default_rng(3)
+    for _ in range(3):
+        v = rng.normal(size=(o.N, 3))
+        hv = H @ free_rows(o, v)
+        lv = free_rows(o, g.hessian_apply(v))
+        assert np.linalg.norm(lv - hv) <= 1e-9 * np.linalg.norm(hv)
+
+
+def test_stiffness_groups(contact_case):
+    sc, o, x, y, pairs, st = contact_case
+    g = lib_scene(sc)
+    kind, prims = map_aug(g, st.aug)
+    g.linearize(x, st.sigma, kind, prims, st.mu, st.s)
+    e, grp = g.stiffness()
+    _, eref = o.hessian(x, pairs, st, with_lambda=True)
+    fi = o.free_idx
+    assert np.abs(e[fi] - eref[fi]).max() <= 1e-9 * eref[fi].max()
+    lg = np.log10(eref[fi])
+    clear = np.abs(lg - np.round(lg)) > 1e-9
+    assert (grp[fi][clear] == np.floor(lg[clear]).astype(int)).all()
+    assert np.unique(grp[fi]).size >= 2
+
+
+def test_pcg_and_warm_start_against_direct_solves(contact_case):
+    sc, o, x, y, pairs, st = contact_case
+    g = lib_scene(sc)
+    kind, prims = map_aug(g, st.aug)
+    g.linearize(x, st.sigma, kind, prims, st.mu, st.s)
+    H, eref = o.hessian(x, pairs, st, with_lambda=True)
+    rng = np.random.default_rng(4)
+    b = rng.normal(size=(o.N, 3))
+    z, it, rel = g.solve(b, mode=0, rtol=1e-13, max_iters=20000)
+    zref = o.solve(H, free_rows(o, b))
+    print(f"global PCG: {it} iterations, rel residual {rel:.2e}")
+    assert np.linalg.norm(free_rows(o, z) - zref) <= 1e-8 * np.linalg.norm(zref)
+    groups = o.stiffness_groups(eref[o.free_idx])
+    zw, itw, _ = g.solve(b, mode=1, rtol=1e-14, max_iters=20000)
+    zwref = o.groupwise_solve(H, free_rows(o, b), groups)
+    print(f"warm start: {itw} iterations")
+    assert np.linalg.norm(free_rows(o, zw) - zwref) <= 1e-7 * np.linalg.norm(zwref)
+    z2, it2, rel2 = g.solve(b, mode=2, rtol=1e-13, max_iters=20000)
+    assert np.linalg.norm(free_rows(o, z2) - zref) <= 1e-8 * np.linalg.norm(zref)
+
+
+def test_candidates_cover_active_pairs(contact_case):
+    sc, o, x, y, pairs, st = contact_case
+    g = lib_scene(sc)
+    kind, nodes, dist = g.candidates(x)
+    d, _ = o.distances(x, pairs)
+    act = np.nonzero(d < o.dhat)[0]
+
+    def key(k, nd):
+        nd = list(map(int, nd))
+        return (int(k), nd[0], tuple(sorted(nd[1:]))) if k == 0 else \
+            (int(k), tuple(sorted([tuple(sorted(nd[:2])), tuple(sorted(nd[2:]))])))
+    got = {key(k, nd): dd for k, nd, dd in zip(kind, nodes, dist)}
+    for i in act:
+        kk = key(pairs.kind[i], pairs.nodes[i])
+        assert kk in got
+        assert abs(got[kk] - d[i]) <= 1e-12 * max(1.0, d[i]) + 1e-15
+    # swept pass along a displacement covers every pair the oracle finds within dhat along the path
+    rng = np.random.default_rng(5)
+    p = np.zeros_like(x)
+    p[: o.n_body] = rng.normal(scale=2e-3, size=(o.n_body, 3))
+    kind2, nodes2, _ = g.candidates(x, p)
+    got2 = {key(k, nd) for k, nd in zip(kind2, nodes2)}
+    for t in np.linspace(0, 1, 5):
+        dt, _ = o.distances(x + t * p, pairs)
+        for i in np.nonzero(dt < o.dhat)[0]:
+            assert key(pairs.kind[i], pairs.nodes[i]) in got2
+
+
+def test_ccd_bound(contact_case):
+    sc, o, x, y, pairs, st = contact_case
+    g = lib_scene(sc)
+    rng = np.random.default_rng(6)
+    for trial in range(4):
+        p = np.zeros_like(x)
+        p[: o.n_body, 1] = -1.5e-3 * (1 + trial)
+        p[: o.n_body] += rng.normal(scale=3e-4, size=(o.n_body, 3))
+        a_gpu = g.ccd_bound(x, p)
+        a_ora = o.ccd(x, p, pairs)
+        print(f"trial {trial}: alpha_max gpu {a_gpu:.15f} oracle {a_ora:.15f}")
+        assert abs(a_gpu - a_ora) <= 1e-9
+
+
+def run_both(sc, n_steps, precision="fp64", newton_rtol=1e-7, pcg_rtol=1e-12, **kw):
+    g = lib_scene(sc, precision=precision, newton_rtol=newton_rtol, pcg_rtol=pcg_rtol, max_newton=200, **kw)
+    o = OracleScene(sc, Params(newton_rtol=newton_rtol, max_newton=200))
+    n = sc["rest_pos"].shape[0]
+    L = np.linalg.norm(sc["x0"].max(0) - sc["x0"].min(0))
+    errs = []
+    for k in range(n_steps):
+        st = g.step(allow=(0, -7))
+        tr = []
+        o.step(trace=tr)
+        xg, vg = g.get_state()
+        err = np.linalg.norm(xg - o.x[:n], axis=1).max() / L
+        gt = g.trace()
+        print(f"step {k}: gpu iters {st['newton_iters']} pcg {st['pcg_iters']} | oracle iters {len(tr)} | eps_x {err:.3e}")
+        print("   gpu   |A| |A'| alpha |e|:", [(int(r[0]), int(r[1]), round(r[5], 6), float(f"{r[6]:.3e}")) for r in gt])
+        print("   oracle|A| |A'| alpha |e|:", [(t['n_active'], t['n_aug'], round(t['alpha'], 6), float(f"{t['enorm']:.3e}")) for t in tr])
+        errs.append(err)
+    return errs
+
+
+def test_tiny_cube_steps_fp64():
+    errs = run_both(scenes.tiny_cube(), 3)
+    assert max(errs) <= 1e-6
+
+
+def test_tiny_cube_steps_mixed():
+    errs = run_both(scenes.tiny_cube(), 3, precision="mixed", newton_rtol=1e-6, pcg_rtol=1e-6)
+    assert max(errs) <= 1e-4
+
+
+def test_small_stacked_boxes_fp64():
+    sc = scenes.stacked_boxes(n_cubes=2, cells=3, seed=0, n_steps=2)
+    errs = run_both(sc, 2, newton_rtol=1e-5)
+    assert max(errs) <= 1e-6
