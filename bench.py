@@ -79,7 +79,7 @@ def run_precision(sc, precision, steps, warmup, stream):
 def cpu_baseline(sc, gpu_newton_per_step):
     import torch
     from oracle import OracleScene, Params
-    o = OracleScene(sc, Params(newton_rtol=1e-4, max_newton=1, pair_mode="kdtree"))
+    o = OracleScene(sc, Params(newton_rtol=1e-4, max_newton=1, pair_mode="kdtree", verbose=True))
     t0 = time.perf_counter()
     o.step()
     sec = time.perf_counter() - t0

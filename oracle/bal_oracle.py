@@ -277,6 +277,7 @@ class Params:
     use_al: bool = True           # False: plain barrier (no A')
     min_alpha: float = 1e-9       # line-search floor (App. B)
     pair_mode: str = "brute"      # "brute" or "kdtree" (superset for large scenes)
+    verbose: bool = False         # print one line per phase of each Newton iteration
 
 
 class OracleScene:
@@ -383,25 +384,45 @@ class OracleScene:
         return self._filter_pairs(kind, a, b, np.concatenate([pt_nodes, ee_nodes]))
 
     def near_pairs(self, x, reach):
-        """Superset of all pairs whose distance at x is below `reach` (k-d tree on centroids)."""
+        """Superset of all pairs whose distance at x is below `reach`.
+
+        Bounding spheres: a point is within `reach` of a triangle only if it
+        lies within r_t + reach of the triangle's centroid (r_t = centroid to
+        farthest vertex); two edges only if their midpoints are within
+        r_1 + r_2 + reach.  Searched with k-d trees; the few edges much longer
+        than the rest (large obstacle faces) are tested against every edge.
+        """
         from scipy.spatial import cKDTree
         V, Tr, Ed = self.s_verts, self.s_tris, self.s_edges
         tc = x[Tr].mean(1)
-        trad = np.linalg.norm(x[Tr] - tc[:, None], axis=2).max()
+        trad = np.linalg.norm(x[Tr] - tc[:, None], axis=2).max(1)
+        vtree = cKDTree(x[V])
+        lst = vtree.query_ball_point(tc, trad + reach)
+        ti = np.repeat(np.arange(Tr.shape[0]), [len(l) for l in lst])
+        vi = np.fromiter((j for l in lst for j in l), dtype=np.int64, count=ti.size)
+        out = [(np.zeros(vi.size, np.int64), V[vi], ti, np.concatenate([V[vi][:, None], Tr[ti]], axis=1))]
         ec = x[Ed].mean(1)
-        erad = np.linalg.norm(x[Ed] - ec[:, None], axis=2).max()
-        out = []
-        lst = cKDTree(x[V]).query_ball_tree(cKDTree(tc), trad + reach)
-        vi = np.repeat(np.arange(V.size), [len(l) for l in lst])
-        ti = np.fromiter((j for l in lst for j in l), dtype=np.int64, count=vi.size)
-        out.append((np.zeros(vi.size, np.int64), V[vi], ti,
-                    np.concatenate([V[vi][:, None], Tr[ti]], axis=1)))
-        ij = cKDTree(ec).query_pairs(2 * erad + reach, output_type="ndarray")
-        ij = np.sort(ij, axis=1) if ij.size else np.zeros((0, 2), np.int64)
+        erad = 0.5 * np.linalg.norm(x[Ed[:, 1]] - x[Ed[:, 0]], axis=1)
+        big = erad > 10.0 * np.median(erad)
+        small = np.nonzero(~big)[0]
+        rmax = erad[small].max() if small.size else 0.0
+        etree = cKDTree(ec[small])
+        lst = etree.query_ball_point(ec[small], erad[small] + rmax + reach)
+        a = np.repeat(small, [len(l) for l in lst])
+        b = small[np.fromiter((j for l in lst for j in l), dtype=np.int64, count=a.size)]
+        keep = (a < b) & (np.linalg.norm(ec[a] - ec[b], axis=1) <= erad[a] + erad[b] + reach)
+        pairs = [np.stack([a[keep], b[keep]], 1)]
+        for e in np.nonzero(big)[0]:
+            o = np.arange(Ed.shape[0])
+            near = (o != e) & (np.linalg.norm(ec - ec[e], axis=1) <= erad + erad[e] + reach)
+            o = o[near]
+            pairs.append(np.stack([np.minimum(o, e), np.maximum(o, e)], 1))
+        ij = np.unique(np.concatenate(pairs), axis=0) if pairs else np.zeros((0, 2), np.int64)
         out.append((np.ones(ij.shape[0], np.int64), ij[:, 0], ij[:, 1],
                     np.concatenate([Ed[ij[:, 0]], Ed[ij[:, 1]]], axis=1)))
-        kind, a, b, nodes = (np.concatenate(z) for z in zip(*out))
-        return self._filter_pairs(kind, a, b, nodes.reshape(-1, 4))
+        kind, pa, pb, nodes = (np.concatenate(z) for z in zip(*out))
+        order = np.lexsort((pb, pa, kind))
+        return self._filter_pairs(kind[order], pa[order], pb[order], nodes.reshape(-1, 4)[order])
 
     def candidate_pairs(self, x, disp=None):
         if self.p.pair_mode == "brute":
@@ -762,8 +783,15 @@ class OracleScene:
             s0 = math.sqrt(float(gE @ gE) / nb)
         return s0
 
+    def _log(self, msg, t0):
+        if self.p.verbose:
+            import time
+            print(f"[oracle] {msg} ({time.perf_counter() - t0:.1f} s)", flush=True)
+
     def step(self, trace=None, return_state=False):
         """Advance one time step with Algorithm 1; returns a stats dict."""
+        import time
+        t0 = time.perf_counter()
         p = self.p
         x_t, v_t = self.x.copy(), self.v.copy()
         y = self.predictor(x_t, v_t)
@@ -800,17 +828,22 @@ class OracleScene:
                 s0 = self.sigma0(x, y, pairs.take(np.nonzero(active)[0]), st)
                 if s0 is not None:
                     st.sigma0 = st.sigma = s0
+            self._log(f"iteration {it}: {len(pairs)} candidate pairs, {int(active.sum())} active", t0)
             L0, g = self.lagrangian(x, y, pairs, st, with_grad=True)
             e = self.gradient_free(g)
             en = float(np.linalg.norm(e))
             if e0 is None:
                 e0 = en
+            self._log(f"iteration {it}: gradient, |e| = {en:.3e}", t0)
             H = self.hessian(x, pairs, st)
+            self._log(f"iteration {it}: projected Hessian assembled ({H.nnz} nonzeros)", t0)
             dx = -self.solve(H, e)
+            self._log(f"iteration {it}: direct solve done", t0)
             P = np.zeros_like(x)
             P[self.free_idx] = dx.reshape(-1, 3)
             swept = self.candidate_pairs(x, disp=P)
             amax = self.ccd(x, P, swept)
+            self._log(f"iteration {it}: CCD over {len(swept)} pairs, alpha_max = {amax:.3e}", t0)
             alpha = amax
             while True:
                 xn = x + alpha * P

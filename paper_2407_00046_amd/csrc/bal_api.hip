@@ -720,7 +720,7 @@ static int build_scene(Scene &s, const bal_scene_desc *d) {
       s.tet_e.grow((size_t)T * 8) || s.tet_g.grow((size_t)T * 12 * 8) || s.tet_tr.grow((size_t)T * 8) ||
       s.tet_blk.grow((size_t)T * 90 * w) || s.val.grow((size_t)(s.nnzb + 1) * 9 * w) || s.Dblk.grow((size_t)N * 9 * w) ||
       s.Dinv.grow((size_t)N * 9 * w) || s.e_nodes.grow((size_t)N * 8) || s.group.grow((size_t)N * 4) ||
-      s.node_e.grow((size_t)N * 8) || s.pcg_ctl.grow(sizeof(PcgCtl)) || s.counter.grow(64) ||
+      s.node_e.grow((size_t)N * 8) || s.pcg_ctl.grow(4096) || s.counter.grow(64) ||
       s.red_out.grow(2048 * 8) || s.flags.grow(64) || grow_aug(s, 1) || grow_pair_list(s.uni, 1) ||
       s.uni_flag.grow(64) || s.uni_aug.grow(64) || s.pair_e.grow(64) || s.pair_g.grow(12 * 8) ||
       s.pair_tr.grow(64) || s.pair_blk.grow(144 * 8))

@@ -21,18 +21,9 @@ struct DBuf {
   template <typename T> T *as() const { return static_cast<T *>(p); }
 };
 
-// Device-side PCG control block (one per solve kind).  Scalars stay on the
-// device so that iterations are launched back to back without host syncs.
-// Group-segmented form: bin b holds the scalars of stiffness group b (warm
-// start) or, with a single bin, of the global solve.
-constexpr int kGroups = 64;        // group bins: label + 32 clamped to [0, 63]
+// Stiffness-group bins of the warm start: group label + 32 clamped to [0, 63].
+constexpr int kGroups = 64;
 constexpr int kGroupOffset = 32;
-struct PcgCtl {
-  double rz[kGroups], pq[kGroups], alpha[kGroups], beta[kGroups], rr[kGroups], ref2[kGroups];
-  int active[kGroups];
-  double tol2, rmin, rnorm;
-  int it, it_min, done, max_it, stall_window, nbins, pad[2];
-};
 // done codes
 enum { PCG_RUN = 0, PCG_CONVERGED = 1, PCG_STALLED = 2, PCG_CAPPED = 3, PCG_BREAKDOWN = 4 };
 

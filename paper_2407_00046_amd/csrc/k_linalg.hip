@@ -9,6 +9,8 @@
 // iteration each row gets a sorted list of the contact blocks it reads.
 // Diagonal blocks (mass + elements + contacts) form the dense block
 // diagonal D that also feeds the block-Jacobi preconditioner.
+#include <algorithm>
+
 #include "bal_internal.h"
 
 namespace bal {
@@ -557,11 +559,21 @@ double spmv_bytes(const Scene &s) {
 }
 
 // ----------------------------------------------------------------- PCG
-// Bins: bin(i) = 0 for the global solve; for the warm start the node's
-// stiffness group + 32 clamped to [0, 63].  Each bin carries its own
-// alpha, beta (segmented dot products).  The last block to finish a
-// reduction (ticket counter) combines the per-block partials in block
-// order, so the scalars are bit-reproducible.
+// No kernel here fences or counts tickets: a kernel writes per-block
+// partial sums, and the next kernel (a kernel boundary orders the writes)
+// re-sums them in a fixed order, so every scalar is bit-reproducible.
+//
+// Global solve, three launches per iteration k+1 (k completed):
+//   cg_spmv   q = A p, partial p.q
+//   cg_update alpha = rz_k / sum(p.q) in every block; x += alpha p,
+//             r -= alpha q, z = D^{-1} r, partials r.z, r.r
+//   cg_dir    beta = sum(r.z) / rz_k, stopping rules, p = z + beta p;
+//             block 0 writes the state after iteration k+1
+// The state after iteration k lives in slot k & 1 (the host passes k), so
+// the slot being written is never the slot being read.
+//
+// Warm start (per stiffness group, 64 bins): per-block per-bin partials are
+// reduced by single-block kernels between the vector kernels.
 template <int NB>
 __device__ __forceinline__ int bin_of(const int *grp, int i) {
   if (NB == 1) return 0;
@@ -569,75 +581,96 @@ __device__ __forceinline__ int bin_of(const int *grp, int i) {
   return b < 0 ? 0 : (b >= NB ? NB - 1 : b);
 }
 
-template <int NB, int NV>
-__device__ bool block_partials_and_ticket(int bin, const double *vals, double *partial, unsigned *counter) {
-  // Each thread contributes vals[0..NV) to one bin (bin < 0: nothing).  The
-  // block's per-bin sums go to partial[block][v][bin]; returns true in the
-  // last block to finish (after a fence), which may then read all partials.
-  __shared__ double sh[NV][NB];
-  __shared__ bool last;
-  if (NB == 1) {
+// Per-bin sums of one value per lane inside a wave: lanes are grouped by bin
+// with ballots (one pass per distinct bin in the wave, usually one or two),
+// each group reduced with a fixed shuffle tree.  Deterministic.
+template <int NB>
+__device__ __forceinline__ void wave_bin_sums(int bin, double v, double *wave_out /* [NB], zeroed */) {
+  const int lane = threadIdx.x & 63;
+  bool pending = bin >= 0;
+  while (__ballot(pending) != 0ull) {
+    unsigned long long act = __ballot(pending);
+    int leader = __ffsll((long long)act) - 1;
+    int b = __shfl(bin, leader, 64);
+    bool mine = pending && bin == b;
+    double x = mine ? v : 0.0;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      double r = block_reduce(bin >= 0 ? vals[v] : 0.0, OpSum(), 0.0);
-      if (threadIdx.x == 0) sh[v][0] = r;
-    }
-  } else {
-    __shared__ int sbin[kBS];
-    __shared__ double sval[NV][kBS];
-    sbin[threadIdx.x] = bin;
-#pragma unroll
-    for (int v = 0; v < NV; ++v) sval[v][threadIdx.x] = bin >= 0 ? vals[v] : 0.0;
-    __syncthreads();
-    for (int b = threadIdx.x; b < NB; b += blockDim.x) {
-      double acc[NV];
-#pragma unroll
-      for (int v = 0; v < NV; ++v) acc[v] = 0.0;
-      for (int t = 0; t < (int)blockDim.x; ++t)
-        if (sbin[t] == b) {
-#pragma unroll
-          for (int v = 0; v < NV; ++v) acc[v] += sval[v][t];
-        }
-#pragma unroll
-      for (int v = 0; v < NV; ++v) sh[v][b] = acc[v];
-    }
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
+    if (lane == 0) wave_out[b] = x;
+    if (mine) pending = false;
   }
-  __syncthreads();
-  for (int k = threadIdx.x; k < NV * NB; k += blockDim.x)
-    partial[(size_t)blockIdx.x * NV * NB + k] = sh[k / NB][k % NB];
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned t = atomicAdd(counter, 1u);
-    last = (t == gridDim.x - 1);
-  }
-  __syncthreads();
-  if (last) __threadfence();
-  return last;
 }
 
+// Block per-bin sums written to part[(v * nbk + block) * NB + bin].
 template <int NB, int NV>
-__device__ void combine_partials(const double *partial, double (*out)[NB]) {
-  // out[v][bin] = sum over blocks in order (thread k handles entry k)
+__device__ void block_partials(int bin, const double *vals, double *part) {
+  constexpr int W = kBS / 64;
+  __shared__ double wsum[W][NV][NB];
+  const int w = threadIdx.x >> 6;
+  if (NB > 1) {
+    for (int k = threadIdx.x; k < W * NV * NB; k += blockDim.x) (&wsum[0][0][0])[k] = 0.0;
+    __syncthreads();
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    double x = bin >= 0 ? vals[v] : 0.0;
+    if (NB == 1) {
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
+      if ((threadIdx.x & 63) == 0) wsum[w][v][0] = x;
+    } else {
+      wave_bin_sums<NB>(bin, x, wsum[w][v]);
+    }
+  }
+  __syncthreads();
+  const int nbk = gridDim.x;
   for (int k = threadIdx.x; k < NV * NB; k += blockDim.x) {
     double acc = 0.0;
-    for (unsigned b = 0; b < gridDim.x; ++b) acc += partial[(size_t)b * NV * NB + k];
-    out[k / NB][k % NB] = acc;
+#pragma unroll
+    for (int q = 0; q < W; ++q) acc += (&wsum[q][0][0])[k];
+    int v = k / NB, b = k % NB;
+    part[((size_t)v * nbk + blockIdx.x) * NB + b] = acc;
+  }
+}
+
+// tot[v][b] = sum over nbk blocks of part[(v * nbk + block) * NB + b]; one
+// wave per entry, lanes striding over blocks, fixed shuffle tree.  All
+// threads of the calling block see the result (after the barrier).
+template <int NB, int NV>
+__device__ void sum_blocks(const double *part, int nbk, double (*tot)[NB]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int k = w; k < NV * NB; k += nw) {
+    int v = k / NB, b = k % NB;
+    double acc = 0.0;
+    for (int j = lane; j < nbk; j += 64) acc += part[((size_t)v * nbk + j) * NB + b];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+    if (lane == 0) tot[v][b] = acc;
   }
   __syncthreads();
 }
 
-// q = A p ; partial p.q ; last block: alpha
+struct CgSlot {
+  double rz, rr, rmin, rnorm;
+  int it, it_min, done, pad;
+};
+struct CgCtl {
+  CgSlot slot[2];
+  double tol2, ref2;
+  int max_it, stall, pad[2];
+};
+struct WarmCtl {
+  double rz[kGroups], alpha[kGroups], beta[kGroups], rr[kGroups], ref2[kGroups];
+  int active[kGroups];
+  double tol2, rnorm;
+  int it, max_it, done, pad;
+};
+
+// ---- shared pieces
 template <typename MT, typename VT, int NB>
-__global__ __launch_bounds__(kBS) void k_pcg_spmv(int N, const int *__restrict__ rp, const int *__restrict__ ci,
-                                                  const MT *__restrict__ val, const MT *__restrict__ D,
-                                                  const int *__restrict__ cp, const int *__restrict__ cc,
-                                                  const int *__restrict__ cs, const MT *__restrict__ pblk,
-                                                  const int *__restrict__ grp, const VT *__restrict__ p,
-                                                  VT *__restrict__ q, PcgCtl *ctl, double *partial,
-                                                  unsigned *counter) {
-  if (ctl->done) return;
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void spmv_partial(int N, int i, const int *rp, const int *ci, const MT *val, const MT *D,
+                                             const int *cp, const int *cc, const int *cs, const MT *pblk,
+                                             const int *grp, const VT *p, VT *q, double *part) {
   double vals[1] = {0.0};
   int bin = -1;
   if (i < N) {
@@ -650,44 +683,20 @@ __global__ __launch_bounds__(kBS) void k_pcg_spmv(int N, const int *__restrict__
     vals[0] = (double)p[3 * i] * (double)acc[0] + (double)p[3 * i + 1] * (double)acc[1] +
               (double)p[3 * i + 2] * (double)acc[2];
   }
-  if (!block_partials_and_ticket<NB, 1>(bin, vals, partial, counter)) return;
-  __shared__ double tot[1][NB];
-  combine_partials<NB, 1>(partial, tot);
-  if (threadIdx.x == 0) {
-    *counter = 0u;
-    bool breakdown = false;
-    for (int b = 0; b < NB; ++b) {
-      double pq = tot[0][b];
-      ctl->pq[b] = pq;
-      if (!ctl->active[b]) { ctl->alpha[b] = 0.0; continue; }
-      if (!(pq > 0.0)) {
-        ctl->alpha[b] = 0.0;
-        if (NB == 1) breakdown = true; else ctl->active[b] = 0;
-        continue;
-      }
-      ctl->alpha[b] = ctl->rz[b] / pq;
-    }
-    if (breakdown) ctl->done = PCG_BREAKDOWN;
-    __threadfence();
-  }
+  block_partials<NB, 1>(bin, vals, part);
 }
 
-// x += alpha p ; r -= alpha q ; z = Dinv r ; partials r.z, r.r ; last block: beta, stopping rules
+// x += al p ; r -= al q ; z = Dinv r ; partial r.z and r.r
 template <typename MT, typename VT, int NB>
-__global__ __launch_bounds__(kBS) void k_pcg_update(int N, const uint8_t *__restrict__ fr,
-                                                    const MT *__restrict__ Dinv, const int *__restrict__ grp,
-                                                    const VT *__restrict__ p, const VT *__restrict__ q,
-                                                    double *__restrict__ x, double *__restrict__ r,
-                                                    VT *__restrict__ z, PcgCtl *ctl, double *partial,
-                                                    unsigned *counter) {
-  if (ctl->done) return;
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void update_partial(int N, int i, const uint8_t *fr, const MT *Dinv, const int *grp,
+                                               const VT *p, const VT *q, double *x, double *r, VT *z,
+                                               const double *alpha_bins, double *part) {
   double vals[2] = {0.0, 0.0};
   int bin = -1;
   if (i < N && fr[i]) {
     int b = bin_of<NB>(grp, i);
     bin = b;
-    double al = ctl->alpha[b];
+    double al = alpha_bins[b];
     double rr[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -696,147 +705,243 @@ __global__ __launch_bounds__(kBS) void k_pcg_update(int N, const uint8_t *__rest
       r[3 * i + c] = rr[c];
     }
     const MT *d = Dinv + (size_t)9 * i;
-    double zz[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      zz[c] = (double)d[3 * c] * rr[0] + (double)d[3 * c + 1] * rr[1] + (double)d[3 * c + 2] * rr[2];
-      z[3 * i + c] = (VT)zz[c];
+      double zz = (double)d[3 * c] * rr[0] + (double)d[3 * c + 1] * rr[1] + (double)d[3 * c + 2] * rr[2];
+      VT zv = (VT)zz;
+      z[3 * i + c] = zv;
+      vals[0] += rr[c] * (double)zv;
+      vals[1] += rr[c] * rr[c];
     }
-    vals[0] = rr[0] * (double)(VT)zz[0] + rr[1] * (double)(VT)zz[1] + rr[2] * (double)(VT)zz[2];
-    vals[1] = rr[0] * rr[0] + rr[1] * rr[1] + rr[2] * rr[2];
   }
-  if (!block_partials_and_ticket<NB, 2>(bin, vals, partial, counter)) return;
-  __shared__ double tot[2][NB];
-  combine_partials<NB, 2>(partial, tot);
-  if (threadIdx.x == 0) {
-    *counter = 0u;
-    ctl->it += 1;
-    double rrsum = 0.0;
-    int any = 0;
-    for (int b = 0; b < NB; ++b) {
-      rrsum += tot[1][b];
-      if (!ctl->active[b]) { ctl->beta[b] = 0.0; continue; }
-      ctl->beta[b] = ctl->rz[b] != 0.0 ? tot[0][b] / ctl->rz[b] : 0.0;
-      ctl->rz[b] = tot[0][b];
-      ctl->rr[b] = tot[1][b];
-      if (NB > 1 && tot[1][b] <= ctl->tol2 * ctl->ref2[b]) ctl->active[b] = 0;
-      any |= ctl->active[b];
+  block_partials<NB, 2>(bin, vals, part);
+}
+
+// ---- global solve
+template <typename MT, typename VT>
+__global__ __launch_bounds__(kBS) void k_cg_spmv(int N, int k, const int *__restrict__ rp, const int *__restrict__ ci,
+                                                 const MT *__restrict__ val, const MT *__restrict__ D,
+                                                 const int *__restrict__ cp, const int *__restrict__ cc,
+                                                 const int *__restrict__ cs, const MT *__restrict__ pblk,
+                                                 const VT *__restrict__ p, VT *__restrict__ q, const CgCtl *ctl,
+                                                 double *part) {
+  if (ctl->slot[k & 1].done) return;
+  spmv_partial<MT, VT, 1>(N, blockIdx.x * blockDim.x + threadIdx.x, rp, ci, val, D, cp, cc, cs, pblk, nullptr, p, q,
+                          part);
+}
+
+template <typename MT, typename VT>
+__global__ __launch_bounds__(kBS) void k_cg_update(int N, int k, const uint8_t *__restrict__ fr,
+                                                   const MT *__restrict__ Dinv, const VT *__restrict__ p,
+                                                   const VT *__restrict__ q, double *__restrict__ x,
+                                                   double *__restrict__ r, VT *__restrict__ z, const CgCtl *ctl,
+                                                   const double *part_pq, double *part) {
+  const CgSlot &s = ctl->slot[k & 1];
+  if (s.done) return;
+  __shared__ double tot[1][1];
+  sum_blocks<1, 1>(part_pq, gridDim.x, tot);
+  double pq = tot[0][0];
+  double al = pq > 0.0 ? s.rz / pq : 0.0;  // breakdown handled in k_cg_dir
+  update_partial<MT, VT, 1>(N, blockIdx.x * blockDim.x + threadIdx.x, fr, Dinv, nullptr, p, q, x, r, z, &al, part);
+}
+
+template <typename VT>
+__global__ __launch_bounds__(kBS) void k_cg_dir(int N, int k, const VT *__restrict__ z, VT *__restrict__ p, CgCtl *ctl,
+                                                const double *part_pq, const double *part) {
+  const CgSlot &s = ctl->slot[k & 1];
+  if (s.done) return;
+  __shared__ double tot[2][1];
+  __shared__ double tpq[1][1];
+  sum_blocks<1, 2>(part, gridDim.x, tot);
+  sum_blocks<1, 1>(part_pq, gridDim.x, tpq);
+  double rz = tot[0][0], rr = tot[1][0];
+  int it = s.it + 1;
+  double rn = sqrt(rr);
+  int done = PCG_RUN;
+  double rmin = s.rmin;
+  int it_min = s.it_min;
+  if (!(tpq[0][0] > 0.0)) done = PCG_BREAKDOWN;
+  else if (rr <= ctl->tol2 * ctl->ref2) done = PCG_CONVERGED;
+  if (rn < rmin) { rmin = rn; it_min = it; }
+  if (!done && ctl->stall > 0 && it - it_min >= ctl->stall) done = PCG_STALLED;
+  if (!done && it >= ctl->max_it) done = PCG_CAPPED;
+  if (!done) {
+    double be = s.rz != 0.0 ? rz / s.rz : 0.0;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) p[3 * i + c] = (VT)((double)z[3 * i + c] + be * (double)p[3 * i + c]);
     }
-    double rn = sqrt(rrsum);
-    ctl->rnorm = rn;
-    if (NB == 1) {
-      if (rrsum <= ctl->tol2 * ctl->ref2[0]) ctl->done = PCG_CONVERGED;
-      if (rn < ctl->rmin) { ctl->rmin = rn; ctl->it_min = ctl->it; }
-      if (!ctl->done && ctl->stall_window > 0 && ctl->it - ctl->it_min >= ctl->stall_window) ctl->done = PCG_STALLED;
-    } else if (!any) {
-      ctl->done = PCG_CONVERGED;
-    }
-    if (!ctl->done && ctl->it >= ctl->max_it) ctl->done = PCG_CAPPED;
-    __threadfence();
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    CgSlot &o = ctl->slot[(k + 1) & 1];
+    o.rz = rz;
+    o.rr = rr;
+    o.rmin = rmin;
+    o.rnorm = rn;
+    o.it = it;
+    o.it_min = it_min;
+    o.done = done;
   }
 }
 
-template <typename VT, int NB>
-__global__ void k_pcg_dir(int N, const int *__restrict__ grp, const VT *__restrict__ z, VT *__restrict__ p,
-                          const PcgCtl *ctl) {
+// ---- warm start (per-group bins)
+template <typename MT, typename VT>
+__global__ __launch_bounds__(kBS) void k_w_spmv(int N, const int *__restrict__ rp, const int *__restrict__ ci,
+                                                const MT *__restrict__ val, const MT *__restrict__ D,
+                                                const int *__restrict__ cp, const int *__restrict__ cc,
+                                                const int *__restrict__ cs, const MT *__restrict__ pblk,
+                                                const int *__restrict__ grp, const VT *__restrict__ p,
+                                                VT *__restrict__ q, const WarmCtl *ctl, double *part) {
+  if (ctl->done) return;
+  spmv_partial<MT, VT, kGroups>(N, blockIdx.x * blockDim.x + threadIdx.x, rp, ci, val, D, cp, cc, cs, pblk, grp, p,
+                                q, part);
+}
+
+__global__ void k_w_alpha(int nbk, WarmCtl *ctl, const double *part) {
+  if (ctl->done) return;
+  __shared__ double tot[1][kGroups];
+  sum_blocks<kGroups, 1>(part, nbk, tot);
+  for (int b = threadIdx.x; b < kGroups; b += blockDim.x) {
+    double pq = tot[0][b];
+    bool ok = ctl->active[b] && pq > 0.0;
+    ctl->alpha[b] = ok ? ctl->rz[b] / pq : 0.0;
+    if (ctl->active[b] && !(pq > 0.0)) ctl->active[b] = 0;
+  }
+}
+
+template <typename MT, typename VT>
+__global__ __launch_bounds__(kBS) void k_w_update(int N, const uint8_t *__restrict__ fr, const MT *__restrict__ Dinv,
+                                                  const int *__restrict__ grp, const VT *__restrict__ p,
+                                                  const VT *__restrict__ q, double *__restrict__ x,
+                                                  double *__restrict__ r, VT *__restrict__ z, const WarmCtl *ctl,
+                                                  double *part) {
+  if (ctl->done) return;
+  update_partial<MT, VT, kGroups>(N, blockIdx.x * blockDim.x + threadIdx.x, fr, Dinv, grp, p, q, x, r, z, ctl->alpha,
+                                  part);
+}
+
+__global__ void k_w_beta(int nbk, WarmCtl *ctl, const double *part) {
+  if (ctl->done) return;
+  __shared__ double tot[2][kGroups];
+  sum_blocks<kGroups, 2>(part, nbk, tot);
+  __shared__ int any;
+  if (threadIdx.x == 0) any = 0;
+  __syncthreads();
+  for (int b = threadIdx.x; b < kGroups; b += blockDim.x) {
+    if (!ctl->active[b]) { ctl->beta[b] = 0.0; continue; }
+    ctl->beta[b] = ctl->rz[b] != 0.0 ? tot[0][b] / ctl->rz[b] : 0.0;
+    ctl->rz[b] = tot[0][b];
+    ctl->rr[b] = tot[1][b];
+    if (tot[1][b] <= ctl->tol2 * ctl->ref2[b]) ctl->active[b] = 0;
+    if (ctl->active[b]) atomicOr(&any, 1);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double rr = 0.0;
+    for (int b = 0; b < kGroups; ++b) rr += tot[1][b];
+    ctl->rnorm = sqrt(rr);
+    ctl->it += 1;
+    if (!any) ctl->done = PCG_CONVERGED;
+    else if (ctl->it >= ctl->max_it) ctl->done = PCG_CAPPED;
+  }
+}
+
+template <typename VT>
+__global__ void k_w_dir(int N, const int *__restrict__ grp, const VT *__restrict__ z, VT *__restrict__ p,
+                        const WarmCtl *ctl) {
   if (ctl->done) return;
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
-  double be = ctl->beta[bin_of<NB>(grp, i)];
+  double be = ctl->beta[bin_of<kGroups>(grp, i)];
 #pragma unroll
   for (int c = 0; c < 3; ++c) p[3 * i + c] = (VT)((double)z[3 * i + c] + be * (double)p[3 * i + c]);
 }
 
-// r = b - q (q = A x0 or zero), z = Dinv r, p = z; partials r.z, r.r, b.b per bin
+// ---- initialisation: r = b - q (q = A x0 or zero), z = Dinv r, p = z;
+// partials r.z, r.r, b.b per bin; a single block then fills the control block.
 template <typename MT, typename VT, int NB>
-__global__ void k_pcg_init(int N, const uint8_t *__restrict__ fr, const MT *__restrict__ Dinv,
-                           const int *__restrict__ grp, const double *__restrict__ bvec, const VT *__restrict__ q,
-                           int use_q, double *__restrict__ r, VT *__restrict__ z, VT *__restrict__ p,
-                           double *__restrict__ part3) {
+__global__ __launch_bounds__(kBS) void k_pcg_init(int N, const uint8_t *__restrict__ fr, const MT *__restrict__ Dinv,
+                                                  const int *__restrict__ grp, const double *__restrict__ bvec,
+                                                  const VT *__restrict__ q, int use_q, double *__restrict__ r,
+                                                  VT *__restrict__ z, VT *__restrict__ p, double *part) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  if (!fr[i]) {
+  double vals[3] = {0.0, 0.0, 0.0};
+  int bin = -1;
+  if (i < N) {
+    if (!fr[i]) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) { r[3 * i + c] = 0.0; z[3 * i + c] = (VT)0; p[3 * i + c] = (VT)0; }
-    part3[3 * (size_t)i] = 0.0; part3[3 * (size_t)i + 1] = 0.0; part3[3 * (size_t)i + 2] = 0.0;
-    return;
-  }
-  double rr[3], bb = 0.0;
+      for (int c = 0; c < 3; ++c) { r[3 * i + c] = 0.0; z[3 * i + c] = (VT)0; p[3 * i + c] = (VT)0; }
+    } else {
+      bin = bin_of<NB>(grp, i);
+      double rr[3];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    double bv = bvec[3 * i + c];
-    bb += bv * bv;
-    rr[c] = bv - (use_q ? (double)q[3 * i + c] : 0.0);
-    r[3 * i + c] = rr[c];
-  }
-  const MT *d = Dinv + (size_t)9 * i;
-  double rz = 0.0, r2 = 0.0;
+      for (int c = 0; c < 3; ++c) {
+        double bv = bvec[3 * i + c];
+        vals[2] += bv * bv;
+        rr[c] = bv - (use_q ? (double)q[3 * i + c] : 0.0);
+        r[3 * i + c] = rr[c];
+      }
+      const MT *d = Dinv + (size_t)9 * i;
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    double zz = (double)d[3 * c] * rr[0] + (double)d[3 * c + 1] * rr[1] + (double)d[3 * c + 2] * rr[2];
-    VT zv = (VT)zz;
-    z[3 * i + c] = zv;
-    p[3 * i + c] = zv;
-    rz += rr[c] * (double)zv;
-    r2 += rr[c] * rr[c];
+      for (int c = 0; c < 3; ++c) {
+        double zz = (double)d[3 * c] * rr[0] + (double)d[3 * c + 1] * rr[1] + (double)d[3 * c + 2] * rr[2];
+        VT zv = (VT)zz;
+        z[3 * i + c] = zv;
+        p[3 * i + c] = zv;
+        vals[0] += rr[c] * (double)zv;
+        vals[1] += rr[c] * rr[c];
+      }
+    }
   }
-  part3[3 * (size_t)i] = rz;
-  part3[3 * (size_t)i + 1] = r2;
-  part3[3 * (size_t)i + 2] = bb;
+  block_partials<NB, 3>(bin, vals, part);
 }
 
-// Per-bin sums of part3 (single block, fixed order) into the control block.
-template <int NB>
-__global__ void k_pcg_init_finish(int N, const uint8_t *__restrict__ fr, const int *__restrict__ grp,
-                                  const double *__restrict__ part3, PcgCtl *ctl, double tol2, double ref2_global,
-                                  int max_it, int stall) {
-  __shared__ double sh[3][NB];
-  for (int k = threadIdx.x; k < 3 * NB; k += blockDim.x) sh[k / NB][k % NB] = 0.0;
-  __syncthreads();
-  // each thread owns a contiguous chunk of nodes; chunks are combined in thread order
-  int chunk = (N + blockDim.x - 1) / blockDim.x;
-  int lo = threadIdx.x * chunk, hi = min(N, lo + chunk);
-  double loc[3][NB];
-  for (int v = 0; v < 3; ++v)
-    for (int b = 0; b < NB; ++b) loc[v][b] = 0.0;
-  for (int i = lo; i < hi; ++i) {
-    if (!fr[i]) continue;
-    int b = bin_of<NB>(grp, i);
-    for (int v = 0; v < 3; ++v) loc[v][b] += part3[3 * (size_t)i + v];
-  }
-  for (int t = 0; t < (int)blockDim.x; ++t) {
-    if ((int)threadIdx.x == t)
-      for (int v = 0; v < 3; ++v)
-        for (int b = 0; b < NB; ++b) sh[v][b] += loc[v][b];
-    __syncthreads();
-  }
+__global__ void k_cg_init_finish(int nbk, CgCtl *ctl, const double *part, double tol2, double ref2, int max_it,
+                                 int stall) {
+  __shared__ double tot[3][1];
+  sum_blocks<1, 3>(part, nbk, tot);
   if (threadIdx.x == 0) {
-    double rrs = 0.0;
-    for (int b = 0; b < NB; ++b) {
-      ctl->rz[b] = sh[0][b];
-      ctl->rr[b] = sh[1][b];
-      rrs += sh[1][b];
-      ctl->ref2[b] = NB == 1 ? ref2_global : sh[2][b];
-      ctl->active[b] = (NB == 1) ? 1 : (sh[2][b] > 0.0 && sh[1][b] > tol2 * sh[2][b]);
+    ctl->tol2 = tol2;
+    ctl->ref2 = ref2;
+    ctl->max_it = max_it;
+    ctl->stall = stall;
+    CgSlot &s = ctl->slot[0];
+    s.rz = tot[0][0];
+    s.rr = tot[1][0];
+    s.rnorm = sqrt(tot[1][0]);
+    s.rmin = s.rnorm;
+    s.it = 0;
+    s.it_min = 0;
+    s.done = PCG_RUN;
+    if (tot[1][0] <= tol2 * ref2) s.done = PCG_CONVERGED;
+    if (max_it <= 0) s.done = PCG_CAPPED;
+    ctl->slot[1] = s;
+    ctl->slot[1].it = -1;
+  }
+}
+
+__global__ void k_w_init_finish(int nbk, WarmCtl *ctl, const double *part, double tol2, int max_it) {
+  __shared__ double tot[3][kGroups];
+  sum_blocks<kGroups, 3>(part, nbk, tot);
+  if (threadIdx.x == 0) {
+    double rr = 0.0;
+    int any = 0;
+    for (int b = 0; b < kGroups; ++b) {
+      ctl->rz[b] = tot[0][b];
+      ctl->rr[b] = tot[1][b];
+      ctl->ref2[b] = tot[2][b];
+      ctl->active[b] = tot[2][b] > 0.0 && tot[1][b] > tol2 * tot[2][b];
       ctl->alpha[b] = 0.0;
       ctl->beta[b] = 0.0;
-      ctl->pq[b] = 0.0;
+      rr += tot[1][b];
+      any |= ctl->active[b];
     }
-    for (int b = NB; b < kGroups; ++b) ctl->active[b] = 0;
     ctl->tol2 = tol2;
-    ctl->rnorm = sqrt(rrs);
-    ctl->rmin = ctl->rnorm;
+    ctl->rnorm = sqrt(rr);
     ctl->it = 0;
-    ctl->it_min = 0;
     ctl->max_it = max_it;
-    ctl->stall_window = stall;
-    ctl->nbins = NB;
-    int any = 0;
-    for (int b = 0; b < NB; ++b) any |= ctl->active[b];
-    ctl->done = PCG_RUN;
-    if (NB == 1 && rrs <= tol2 * ref2_global) ctl->done = PCG_CONVERGED;
-    if (NB > 1 && !any) ctl->done = PCG_CONVERGED;
-    if (max_it <= 0) ctl->done = PCG_CAPPED;
+    ctl->done = any ? (max_it > 0 ? PCG_RUN : PCG_CAPPED) : PCG_CONVERGED;
   }
 }
 
@@ -869,95 +974,143 @@ static void harvest_events(Scene &s) {
   s.ev_used = 0;
 }
 
+// r = b - A x0 with x0 given in xsol (start) or zero; leaves r, z, p and the partials.
 template <typename MT, typename VT, int NB>
-static int pcg_run(Scene &s, const double *rhs, double *xsol, double tol, double ref2, int max_iters, bool start,
-                   bool resume, int *iters_out, double *rnorm_out) {
-  int N = s.N, n3 = 3 * N;
-  PcgCtl *ctl = s.pcg_ctl.as<PcgCtl>();
-  int nb = blocks_for(N, kBS);
-  size_t need = (size_t)nb * 2 * NB * sizeof(double);
-  if (s.partial.grow(need < (size_t)3 * N * sizeof(double) ? (size_t)3 * N * sizeof(double) : need)) return BAL_E_OOM;
-  double *partial = s.partial.as<double>();
-  unsigned *counter = s.counter.as<unsigned>();
+static int pcg_start(Scene &s, const double *rhs, double *xsol, bool start, double *part) {
+  int N = s.N, n3 = 3 * N, nb = blocks_for(N, kBS);
   VT *p = static_cast<VT *>(s.pv.p), *q = static_cast<VT *>(s.q.p), *z = static_cast<VT *>(s.z.p);
-  double *r = s.r.as<double>();
   const MT *val = static_cast<const MT *>(s.val.p), *D = static_cast<const MT *>(s.Dblk.p);
   const MT *Dinv = static_cast<const MT *>(s.Dinv.p), *pblk = static_cast<const MT *>(s.pair_blk.p);
   const int *grp = s.group.as<int>();
+  bool use_q = false;
+  if (!start) {
+    hipMemsetAsync(xsol, 0, n3 * sizeof(double), s.stream);
+  } else {
+    if (sizeof(VT) == 4)
+      hipLaunchKernelGGL(k_to_vt_f, dim3(blocks_for(n3, kBS)), dim3(kBS), 0, s.stream, xsol, (float *)p, n3);
+    else
+      hipLaunchKernelGGL(k_copy_d, dim3(blocks_for(n3, kBS)), dim3(kBS), 0, s.stream, xsol, (double *)p, n3);
+    hipLaunchKernelGGL((k_spmv<MT, VT>), dim3(nb), dim3(kBS), 0, s.stream, N, s.row_ptr.as<int>(), s.col_idx.as<int>(),
+                       val, D, s.coff_ptr.as<int>(), s.coff_col.as<int>(), s.coff_src.as<int>(), pblk, grp,
+                       NB > 1 ? 1 : 0, p, q);
+    use_q = true;
+  }
+  hipLaunchKernelGGL((k_pcg_init<MT, VT, NB>), dim3(nb), dim3(kBS), 0, s.stream, N, s.freev.as<uint8_t>(), Dinv, grp,
+                     rhs, q, use_q ? 1 : 0, s.r.as<double>(), z, p, part);
+  return BAL_OK;
+}
+
+template <typename MT, typename VT>
+static int cg_run(Scene &s, const double *rhs, double *xsol, double tol, double ref2, int max_iters, bool start,
+                  bool resume, int *iters_out, double *rnorm_out) {
+  int N = s.N, nb = blocks_for(N, kBS);
+  if (s.partial.grow((size_t)nb * 6 * sizeof(double)) || s.pcg_ctl.grow(sizeof(CgCtl))) return BAL_E_OOM;
+  double *part_pq = s.partial.as<double>(), *part = part_pq + 3 * (size_t)nb;
+  CgCtl *ctl = s.pcg_ctl.as<CgCtl>();
+  CgCtl *h = s.pin.as<CgCtl>();
+  VT *p = static_cast<VT *>(s.pv.p), *q = static_cast<VT *>(s.q.p), *z = static_cast<VT *>(s.z.p);
+  const MT *val = static_cast<const MT *>(s.val.p), *D = static_cast<const MT *>(s.Dblk.p);
+  const MT *Dinv = static_cast<const MT *>(s.Dinv.p), *pblk = static_cast<const MT *>(s.pair_blk.p);
+  double *r = s.r.as<double>();
+  int k;
   if (resume) {
     // continue the same Krylov sequence for max_iters more iterations, tolerance off
-    PcgCtl *h = s.pin.as<PcgCtl>();
-    hipMemcpyAsync(h, ctl, sizeof(PcgCtl), hipMemcpyDeviceToHost, s.stream);
+    hipMemcpyAsync(h, ctl, sizeof(CgCtl), hipMemcpyDeviceToHost, s.stream);
     hipStreamSynchronize(s.stream);
-    h->max_it = h->it + max_iters;
+    int cur = h->slot[0].it >= h->slot[1].it ? 0 : 1;
+    CgSlot sl = h->slot[cur];
+    k = sl.it;
+    if (sl.done == PCG_BREAKDOWN) { *iters_out = k; *rnorm_out = sl.rnorm; return BAL_E_NO_CONVERGENCE; }
+    sl.done = PCG_RUN;
+    sl.it_min = sl.it;
+    h->slot[k & 1] = sl;
+    h->max_it = k + max_iters;
     h->tol2 = 0.0;
-    h->done = h->done == PCG_BREAKDOWN ? PCG_BREAKDOWN : PCG_RUN;
-    h->it_min = h->it;
-    hipMemcpyAsync(ctl, h, sizeof(PcgCtl), hipMemcpyHostToDevice, s.stream);
+    hipMemcpyAsync(ctl, h, sizeof(CgCtl), hipMemcpyHostToDevice, s.stream);
   } else {
-    hipMemsetAsync(counter, 0, sizeof(unsigned), s.stream);
-    bool use_q = false;
-    if (!start) {
-      hipMemsetAsync(xsol, 0, n3 * sizeof(double), s.stream);
-    } else {
-      // x0 given in xsol: q = A x0
-      if (sizeof(VT) == 4)
-        hipLaunchKernelGGL(k_to_vt_f, dim3(blocks_for(n3, kBS)), dim3(kBS), 0, s.stream, xsol, (float *)p, n3);
-      else
-        hipLaunchKernelGGL(k_copy_d, dim3(blocks_for(n3, kBS)), dim3(kBS), 0, s.stream, xsol, (double *)p, n3);
-      hipLaunchKernelGGL((k_spmv<MT, VT>), dim3(nb), dim3(kBS), 0, s.stream, N, s.row_ptr.as<int>(),
-                         s.col_idx.as<int>(), val, D, s.coff_ptr.as<int>(), s.coff_col.as<int>(), s.coff_src.as<int>(),
-                         pblk, grp, NB > 1 ? 1 : 0, p, q);
-      use_q = true;
-    }
-    hipLaunchKernelGGL((k_pcg_init<MT, VT, NB>), dim3(nb), dim3(kBS), 0, s.stream, N, s.freev.as<uint8_t>(), Dinv, grp,
-                       rhs, q, use_q ? 1 : 0, r, z, p, partial);
-    hipLaunchKernelGGL((k_pcg_init_finish<NB>), dim3(1), dim3(kBS), 0, s.stream, N, s.freev.as<uint8_t>(), grp,
-                       partial, ctl, tol * tol, ref2, max_iters, NB == 1 ? s.desc.pcg_stall_window : 0);
+    pcg_start<MT, VT, 1>(s, rhs, xsol, start, part);
+    hipLaunchKernelGGL(k_cg_init_finish, dim3(1), dim3(kBS), 0, s.stream, nb, ctl, part, tol * tol, ref2, max_iters,
+                       s.desc.pcg_stall_window);
+    k = 0;
   }
   const int chunk = 16;
-  PcgCtl *h = s.pin.as<PcgCtl>();
   for (;;) {
-    for (int k = 0; k < chunk; ++k) {
+    for (int c = 0; c < chunk; ++c, ++k) {
       hipEvent_t e0 = nullptr, e1 = nullptr;
       if (s.time_kernels) { e0 = take_event(s); hipEventRecord(e0, s.stream); }
-      hipLaunchKernelGGL((k_pcg_spmv<MT, VT, NB>), dim3(nb), dim3(kBS), 0, s.stream, N, s.row_ptr.as<int>(),
+      hipLaunchKernelGGL((k_cg_spmv<MT, VT>), dim3(nb), dim3(kBS), 0, s.stream, N, k, s.row_ptr.as<int>(),
                          s.col_idx.as<int>(), val, D, s.coff_ptr.as<int>(), s.coff_col.as<int>(), s.coff_src.as<int>(),
-                         pblk, grp, p, q, ctl, partial, counter);
+                         pblk, p, q, ctl, part_pq);
       if (s.time_kernels) { e1 = take_event(s); hipEventRecord(e1, s.stream); }
-      hipLaunchKernelGGL((k_pcg_update<MT, VT, NB>), dim3(nb), dim3(kBS), 0, s.stream, N, s.freev.as<uint8_t>(), Dinv,
-                         grp, p, q, xsol, r, z, ctl, partial, counter);
-      hipLaunchKernelGGL((k_pcg_dir<VT, NB>), dim3(nb), dim3(kBS), 0, s.stream, N, grp, z, p, ctl);
+      hipLaunchKernelGGL((k_cg_update<MT, VT>), dim3(nb), dim3(kBS), 0, s.stream, N, k, s.freev.as<uint8_t>(), Dinv, p,
+                         q, xsol, r, z, ctl, part_pq, part);
+      hipLaunchKernelGGL((k_cg_dir<VT>), dim3(nb), dim3(kBS), 0, s.stream, N, k, z, p, ctl, part_pq, part);
     }
-    hipMemcpyAsync(h, ctl, sizeof(PcgCtl), hipMemcpyDeviceToHost, s.stream);
+    hipMemcpyAsync(h, ctl, sizeof(CgCtl), hipMemcpyDeviceToHost, s.stream);
     if (hipStreamSynchronize(s.stream) != hipSuccess) return BAL_E_HIP;
     if (s.time_kernels) harvest_events(s);
+    const CgSlot &sl = h->slot[h->slot[0].it >= h->slot[1].it ? 0 : 1];
+    if (sl.done) {
+      // SpMV launches after the stop exit at once; do not count them as timed work
+      if (s.time_kernels) s.spmv_launches -= std::max(0, k - sl.it);
+      *iters_out = sl.it;
+      *rnorm_out = sl.rnorm;
+      return sl.done == PCG_BREAKDOWN ? BAL_E_NO_CONVERGENCE : BAL_OK;
+    }
+  }
+}
+
+template <typename MT, typename VT>
+static int warm_run(Scene &s, const double *rhs, double *xsol, double tol, int max_iters, int *iters_out) {
+  int N = s.N, nb = blocks_for(N, kBS);
+  if (s.partial.grow((size_t)nb * 3 * kGroups * sizeof(double)) || s.warm_ctl.grow(sizeof(WarmCtl))) return BAL_E_OOM;
+  double *part = s.partial.as<double>();
+  WarmCtl *ctl = s.warm_ctl.as<WarmCtl>();
+  VT *p = static_cast<VT *>(s.pv.p), *q = static_cast<VT *>(s.q.p), *z = static_cast<VT *>(s.z.p);
+  const MT *val = static_cast<const MT *>(s.val.p), *D = static_cast<const MT *>(s.Dblk.p);
+  const MT *Dinv = static_cast<const MT *>(s.Dinv.p), *pblk = static_cast<const MT *>(s.pair_blk.p);
+  const int *grp = s.group.as<int>();
+  double *r = s.r.as<double>();
+  pcg_start<MT, VT, kGroups>(s, rhs, xsol, false, part);
+  hipLaunchKernelGGL(k_w_init_finish, dim3(1), dim3(kBS), 0, s.stream, nb, ctl, part, tol * tol, max_iters);
+  WarmCtl *h = s.pin.as<WarmCtl>();
+  const int chunk = 8;
+  for (;;) {
+    for (int c = 0; c < chunk; ++c) {
+      hipLaunchKernelGGL((k_w_spmv<MT, VT>), dim3(nb), dim3(kBS), 0, s.stream, N, s.row_ptr.as<int>(),
+                         s.col_idx.as<int>(), val, D, s.coff_ptr.as<int>(), s.coff_col.as<int>(), s.coff_src.as<int>(),
+                         pblk, grp, p, q, ctl, part);
+      hipLaunchKernelGGL(k_w_alpha, dim3(1), dim3(kBS), 0, s.stream, nb, ctl, part);
+      hipLaunchKernelGGL((k_w_update<MT, VT>), dim3(nb), dim3(kBS), 0, s.stream, N, s.freev.as<uint8_t>(), Dinv, grp, p,
+                         q, xsol, r, z, ctl, part);
+      hipLaunchKernelGGL(k_w_beta, dim3(1), dim3(kBS), 0, s.stream, nb, ctl, part);
+      hipLaunchKernelGGL((k_w_dir<VT>), dim3(nb), dim3(kBS), 0, s.stream, N, grp, z, p, ctl);
+    }
+    hipMemcpyAsync(h, ctl, sizeof(WarmCtl), hipMemcpyDeviceToHost, s.stream);
+    if (hipStreamSynchronize(s.stream) != hipSuccess) return BAL_E_HIP;
     if (h->done) break;
   }
   *iters_out = h->it;
-  *rnorm_out = h->rnorm;
-  return h->done == PCG_BREAKDOWN ? BAL_E_NO_CONVERGENCE : BAL_OK;
+  return BAL_OK;
 }
 
 int pcg_solve(Scene &s, const double *rhs, double *xsol, double rtol_ref, int max_iters, int warm, int resume,
               int *iters_out, double *rel_out) {
-  // rtol_ref: ||r|| <= pcg_rtol * rtol_ref is the stopping rule (reading: zero-guess residual)
+  // ||r|| <= pcg_rtol * rtol_ref is the stopping rule (reading: zero-guess residual)
   double rn = 0.0;
   int rc;
   double ref2 = rtol_ref * rtol_ref;
   if (s.mixed)
-    rc = pcg_run<float, float, 1>(s, rhs, xsol, s.desc.pcg_rtol, ref2, max_iters, warm != 0, resume != 0, iters_out, &rn);
+    rc = cg_run<float, float>(s, rhs, xsol, s.desc.pcg_rtol, ref2, max_iters, warm != 0, resume != 0, iters_out, &rn);
   else
-    rc = pcg_run<double, double, 1>(s, rhs, xsol, s.desc.pcg_rtol, ref2, max_iters, warm != 0, resume != 0, iters_out,
-                                    &rn);
+    rc = cg_run<double, double>(s, rhs, xsol, s.desc.pcg_rtol, ref2, max_iters, warm != 0, resume != 0, iters_out, &rn);
   *rel_out = rtol_ref > 0 ? rn / rtol_ref : rn;
   return rc;
 }
 
 int warm_start_solve(Scene &s, const double *rhs, double *xsol, double wtol, int max_iters, int *iters_out) {
-  double rn = 0.0;
-  if (s.mixed) return pcg_run<float, float, kGroups>(s, rhs, xsol, wtol, 0.0, max_iters, false, false, iters_out, &rn);
-  return pcg_run<double, double, kGroups>(s, rhs, xsol, wtol, 0.0, max_iters, false, false, iters_out, &rn);
+  if (s.mixed) return warm_run<float, float>(s, rhs, xsol, wtol, max_iters, iters_out);
+  return warm_run<double, double>(s, rhs, xsol, wtol, max_iters, iters_out);
 }
 
 }  // namespace bal

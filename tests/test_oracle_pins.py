@@ -445,3 +445,18 @@ def test_ccd_bound_precedes_first_crossing():
         if d0 > 1e-2 * o.dhat:
             assert amax > 0
     assert hits > 5
+
+
+def test_kdtree_pair_superset_matches_brute_force():
+    """The large-scene pair search returns every brute-force pair within reach."""
+    sc = scenes.stacked_boxes(n_cubes=2, cells=3, seed=0)
+    o = OracleScene(sc)
+    x = o.x.copy()
+    rng = np.random.default_rng(0)
+    x[: o.n_body] += rng.normal(scale=2e-3, size=(o.n_body, 3))
+    allp = o.all_pairs()
+    d, _ = o.distances(x, allp)
+    for reach in (1e-3, 5e-3, 2e-2):
+        need = set(map(int, allp.keys()[d < reach]))
+        have = set(map(int, o.near_pairs(x, reach).keys()))
+        assert need <= have
