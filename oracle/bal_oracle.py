@@ -865,8 +865,10 @@ class OracleScene:
                 x = xn
                 converged = True
                 break
-            if alpha == 0.0 and len(st.aug) == 0:
-                break  # no step and nothing left to update: stalled (reading)
+            moved = alpha * float(np.linalg.norm(P[self.free_idx]))
+            if moved <= 1e-15 * float(np.linalg.norm(x[self.free_idx])) and len(st.aug) == 0:
+                x = xn
+                break  # no measurable step and nothing left to update: stalled (reading)
             # dual and penalty updates (Alg. 1, lines 12-17)
             dn, _ = self.distances(xn, swept)
             if len(st.aug):
@@ -895,6 +897,8 @@ class OracleScene:
         """
         pairs = self.candidate_pairs(x_next)
         H = self.hessian(x_next, pairs, st, project=False)
+        pad = lambda a: np.concatenate([np.asarray(a, dtype=np.float64), np.zeros((self.N - len(a), 3))])
+        gx_next, gv_next = pad(gx_next), pad(gv_next)
         rhs = (gx_next + gv_next / self.h)[self.free_idx].reshape(-1)
         lam_f = self.solve(H, rhs) if H.shape[0] <= 4000 else scipy.sparse.linalg.spsolve(H.tocsc(), rhs)
         lam = np.zeros((self.N, 3))

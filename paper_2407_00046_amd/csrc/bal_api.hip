@@ -452,7 +452,14 @@ static int newton_solve(Scene &s, bal_step_stats *st, bool record) {
       S.converged = 1;
       break;
     }
-    if (alpha == 0.0 && s.n_aug == 0) break;  // no step and nothing left to update: stalled
+    if (s.n_aug == 0) {
+      // no measurable step and nothing left to update: stalled
+      double moved = alpha * std::sqrt(dot_free(s, dx, dx));
+      if (moved <= 1e-15 * std::sqrt(dot_free(s, x, x))) {
+        copy3(s, x, xtr);
+        break;
+      }
+    }
     // dual and penalty updates at the new iterate (Alg. 1, lines 12-17)
     if (s.n_aug) launch_aug_update(s, xtr);
     launch_pair_distance(s, s.cand2, xtr, s.cand2.d.as<double>(), s.cand2.cs.as<int>());
@@ -510,6 +517,11 @@ static int build_scene(Scene &s, const bal_scene_desc *d) {
   s.dev = d->device;
   if (hipSetDevice(s.dev) != hipSuccess) return BAL_E_HIP;
   s.stream = static_cast<hipStream_t>(d->stream);
+  if (s.stream == nullptr) {
+    // graph capture needs a stream of our own; a blocking stream stays ordered with the NULL stream
+    if (hipStreamCreateWithFlags(&s.stream, hipStreamDefault) != hipSuccess) return BAL_E_HIP;
+    s.own_stream = true;
+  }
   s.mixed = d->precision == BAL_MIXED;
   s.nb = d->n_verts;
   s.no = d->n_obs_verts;
@@ -849,6 +861,10 @@ void bal_destroy_scene(bal_scene *h) {
   }
   if (s.pin.p) hipHostFree(s.pin.p);
   for (hipEvent_t e : s.ev_pool) hipEventDestroy(e);
+  for (hipEvent_t e : s.graph_ev) hipEventDestroy(e);
+  if (s.cg_exec) hipGraphExecDestroy(s.cg_exec);
+  if (s.warm_exec) hipGraphExecDestroy(s.warm_exec);
+  if (s.own_stream && s.stream) hipStreamDestroy(s.stream);
   delete h;
 }
 

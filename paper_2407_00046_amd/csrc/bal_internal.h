@@ -77,6 +77,12 @@ struct Scene {
   DBuf r, z, pv, q, pcg_ctl, warm_ctl, partial, counter, scan_tmp, red_out, flags;
   DBuf node_e, cand_e, mask, mask_off, tau, rhs;
   DBuf pin;     // pinned host scratch (hipHostMalloc)
+  // graph replay of PCG chunks (re-captured when a buffer moves)
+  bool use_graphs = true;
+  bool own_stream = false;
+  hipGraphExec_t cg_exec = nullptr, warm_exec = nullptr;
+  std::vector<uintptr_t> cg_sig, warm_sig;
+  std::vector<hipEvent_t> graph_ev;
   // timing
   bool time_kernels = false;
   std::vector<hipEvent_t> ev_pool;

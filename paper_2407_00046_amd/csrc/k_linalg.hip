@@ -487,36 +487,53 @@ void launch_offdiag_assembly(Scene &s) {
 // y_i = D_i v_i + sum_static A_ij v_j + sum_contact C_ij v_j; with masked,
 // blocks whose row and column lie in different stiffness groups are skipped
 // (the warm start's domain-decomposed product, Sec. 4.2).
+// One block row computed by a group of kG consecutive lanes: lane g of the
+// group takes blocks g, g + kG, ... of the row (static and contact parts),
+// the partial products are summed with shuffles, and lane 0 of the group
+// adds D_i v_i and holds the result.  Consecutive lanes read consecutive
+// 36/72-byte blocks of the row, and a 39K-row system fills kG times as
+// many waves as one thread per row would.
+constexpr int kG = 4;
+
 template <typename MT, typename VT>
-__device__ __forceinline__ void spmv_row(int i, const int *__restrict__ rp, const int *__restrict__ ci,
+__device__ __forceinline__ void spmv_row(int i, int g, const int *__restrict__ rp, const int *__restrict__ ci,
                                          const MT *__restrict__ val, const MT *__restrict__ D,
                                          const int *__restrict__ cp, const int *__restrict__ cc,
                                          const int *__restrict__ cs, const MT *__restrict__ pblk,
                                          const int *__restrict__ grp, int masked, const VT *__restrict__ v,
                                          VT *acc) {
-  VT v0 = v[3 * i], v1 = v[3 * i + 1], v2 = v[3 * i + 2];
-  const MT *d = D + (size_t)9 * i;
-  acc[0] = (VT)d[0] * v0 + (VT)d[1] * v1 + (VT)d[2] * v2;
-  acc[1] = (VT)d[3] * v0 + (VT)d[4] * v1 + (VT)d[5] * v2;
-  acc[2] = (VT)d[6] * v0 + (VT)d[7] * v1 + (VT)d[8] * v2;
-  int gi = masked ? grp[i] : 0;
-  for (int k = rp[i]; k < rp[i + 1]; ++k) {
-    int j = ci[k];
-    if (masked && grp[j] != gi) continue;
-    const MT *a = val + (size_t)9 * k;
-    VT w0 = v[3 * j], w1 = v[3 * j + 1], w2 = v[3 * j + 2];
-    acc[0] += (VT)a[0] * w0 + (VT)a[1] * w1 + (VT)a[2] * w2;
-    acc[1] += (VT)a[3] * w0 + (VT)a[4] * w1 + (VT)a[5] * w2;
-    acc[2] += (VT)a[6] * w0 + (VT)a[7] * w1 + (VT)a[8] * w2;
+  acc[0] = acc[1] = acc[2] = (VT)0;
+  if (i >= 0) {
+    int gi = masked ? grp[i] : 0;
+    for (int k = rp[i] + g; k < rp[i + 1]; k += kG) {
+      int j = ci[k];
+      if (masked && grp[j] != gi) continue;
+      const MT *a = val + (size_t)9 * k;
+      VT w0 = v[3 * j], w1 = v[3 * j + 1], w2 = v[3 * j + 2];
+      acc[0] += (VT)a[0] * w0 + (VT)a[1] * w1 + (VT)a[2] * w2;
+      acc[1] += (VT)a[3] * w0 + (VT)a[4] * w1 + (VT)a[5] * w2;
+      acc[2] += (VT)a[6] * w0 + (VT)a[7] * w1 + (VT)a[8] * w2;
+    }
+    for (int k = cp[i] + g; k < cp[i + 1]; k += kG) {
+      int j = cc[k];
+      if (masked && grp[j] != gi) continue;
+      const MT *a = pblk + (size_t)9 * cs[k];
+      VT w0 = v[3 * j], w1 = v[3 * j + 1], w2 = v[3 * j + 2];
+      acc[0] += (VT)a[0] * w0 + (VT)a[1] * w1 + (VT)a[2] * w2;
+      acc[1] += (VT)a[3] * w0 + (VT)a[4] * w1 + (VT)a[5] * w2;
+      acc[2] += (VT)a[6] * w0 + (VT)a[7] * w1 + (VT)a[8] * w2;
+    }
   }
-  for (int k = cp[i]; k < cp[i + 1]; ++k) {
-    int j = cc[k];
-    if (masked && grp[j] != gi) continue;
-    const MT *a = pblk + (size_t)9 * cs[k];
-    VT w0 = v[3 * j], w1 = v[3 * j + 1], w2 = v[3 * j + 2];
-    acc[0] += (VT)a[0] * w0 + (VT)a[1] * w1 + (VT)a[2] * w2;
-    acc[1] += (VT)a[3] * w0 + (VT)a[4] * w1 + (VT)a[5] * w2;
-    acc[2] += (VT)a[6] * w0 + (VT)a[7] * w1 + (VT)a[8] * w2;
+#pragma unroll
+  for (int o = kG / 2; o > 0; o >>= 1)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc[c] += __shfl_xor(acc[c], o, kG);
+  if (i >= 0 && g == 0) {
+    VT v0 = v[3 * i], v1 = v[3 * i + 1], v2 = v[3 * i + 2];
+    const MT *d = D + (size_t)9 * i;
+    acc[0] += (VT)d[0] * v0 + (VT)d[1] * v1 + (VT)d[2] * v2;
+    acc[1] += (VT)d[3] * v0 + (VT)d[4] * v1 + (VT)d[5] * v2;
+    acc[2] += (VT)d[6] * v0 + (VT)d[7] * v1 + (VT)d[8] * v2;
   }
 }
 
@@ -527,17 +544,19 @@ __global__ __launch_bounds__(kBS) void k_spmv(int N, const int *__restrict__ rp,
                                               const int *__restrict__ cs, const MT *__restrict__ pblk,
                                               const int *__restrict__ grp, int masked, const VT *__restrict__ v,
                                               VT *__restrict__ out) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
+  long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  int i = (int)(t / kG), g = (int)(t % kG);
   VT acc[3];
-  spmv_row<MT, VT>(i, rp, ci, val, D, cp, cc, cs, pblk, grp, masked, v, acc);
-  out[3 * i] = acc[0];
-  out[3 * i + 1] = acc[1];
-  out[3 * i + 2] = acc[2];
+  spmv_row<MT, VT>(i < N ? i : -1, g, rp, ci, val, D, cp, cc, cs, pblk, grp, masked, v, acc);
+  if (i < N && g == 0) {
+    out[3 * i] = acc[0];
+    out[3 * i + 1] = acc[1];
+    out[3 * i + 2] = acc[2];
+  }
 }
 
 void launch_spmv(Scene &s, const void *vin, void *vout, int masked) {
-  dim3 g(blocks_for(s.N, kBS)), b(kBS);
+  dim3 g(blocks_for((long)s.N * kG, kBS)), b(kBS);
   if (s.mixed)
     hipLaunchKernelGGL((k_spmv<float, float>), g, b, 0, s.stream, s.N, s.row_ptr.as<int>(), s.col_idx.as<int>(),
                        s.val.as<float>(), s.Dblk.as<float>(), s.coff_ptr.as<int>(), s.coff_col.as<int>(),
@@ -657,7 +676,9 @@ struct CgSlot {
 struct CgCtl {
   CgSlot slot[2];
   double tol2, ref2;
-  int max_it, stall, pad[2];
+  int max_it, stall;
+  int stop;  // raised with the final state: every later launch exits at once
+  int pad;
 };
 struct WarmCtl {
   double rz[kGroups], alpha[kGroups], beta[kGroups], rr[kGroups], ref2[kGroups];
@@ -668,14 +689,15 @@ struct WarmCtl {
 
 // ---- shared pieces
 template <typename MT, typename VT, int NB>
-__device__ __forceinline__ void spmv_partial(int N, int i, const int *rp, const int *ci, const MT *val, const MT *D,
+__device__ __forceinline__ void spmv_partial(int N, long t, const int *rp, const int *ci, const MT *val, const MT *D,
                                              const int *cp, const int *cc, const int *cs, const MT *pblk,
                                              const int *grp, const VT *p, VT *q, double *part) {
   double vals[1] = {0.0};
   int bin = -1;
-  if (i < N) {
-    VT acc[3];
-    spmv_row<MT, VT>(i, rp, ci, val, D, cp, cc, cs, pblk, grp, NB > 1, p, acc);
+  int i = (int)(t / kG), g = (int)(t % kG);
+  VT acc[3];
+  spmv_row<MT, VT>(i < N ? i : -1, g, rp, ci, val, D, cp, cc, cs, pblk, grp, NB > 1, p, acc);
+  if (i < N && g == 0) {
     q[3 * i] = acc[0];
     q[3 * i + 1] = acc[1];
     q[3 * i + 2] = acc[2];
@@ -725,9 +747,9 @@ __global__ __launch_bounds__(kBS) void k_cg_spmv(int N, int k, const int *__rest
                                                  const int *__restrict__ cs, const MT *__restrict__ pblk,
                                                  const VT *__restrict__ p, VT *__restrict__ q, const CgCtl *ctl,
                                                  double *part) {
-  if (ctl->slot[k & 1].done) return;
-  spmv_partial<MT, VT, 1>(N, blockIdx.x * blockDim.x + threadIdx.x, rp, ci, val, D, cp, cc, cs, pblk, nullptr, p, q,
-                          part);
+  if (ctl->stop || ctl->slot[k & 1].done) return;
+  spmv_partial<MT, VT, 1>(N, (long)blockIdx.x * blockDim.x + threadIdx.x, rp, ci, val, D, cp, cc, cs, pblk, nullptr, p,
+                          q, part);
 }
 
 template <typename MT, typename VT>
@@ -735,11 +757,11 @@ __global__ __launch_bounds__(kBS) void k_cg_update(int N, int k, const uint8_t *
                                                    const MT *__restrict__ Dinv, const VT *__restrict__ p,
                                                    const VT *__restrict__ q, double *__restrict__ x,
                                                    double *__restrict__ r, VT *__restrict__ z, const CgCtl *ctl,
-                                                   const double *part_pq, double *part) {
+                                                   const double *part_pq, int nb_pq, double *part) {
   const CgSlot &s = ctl->slot[k & 1];
-  if (s.done) return;
+  if (ctl->stop || s.done) return;
   __shared__ double tot[1][1];
-  sum_blocks<1, 1>(part_pq, gridDim.x, tot);
+  sum_blocks<1, 1>(part_pq, nb_pq, tot);
   double pq = tot[0][0];
   double al = pq > 0.0 ? s.rz / pq : 0.0;  // breakdown handled in k_cg_dir
   update_partial<MT, VT, 1>(N, blockIdx.x * blockDim.x + threadIdx.x, fr, Dinv, nullptr, p, q, x, r, z, &al, part);
@@ -747,13 +769,13 @@ __global__ __launch_bounds__(kBS) void k_cg_update(int N, int k, const uint8_t *
 
 template <typename VT>
 __global__ __launch_bounds__(kBS) void k_cg_dir(int N, int k, const VT *__restrict__ z, VT *__restrict__ p, CgCtl *ctl,
-                                                const double *part_pq, const double *part) {
+                                                const double *part_pq, int nb_pq, const double *part) {
   const CgSlot &s = ctl->slot[k & 1];
-  if (s.done) return;
+  if (ctl->stop || s.done) return;
   __shared__ double tot[2][1];
   __shared__ double tpq[1][1];
   sum_blocks<1, 2>(part, gridDim.x, tot);
-  sum_blocks<1, 1>(part_pq, gridDim.x, tpq);
+  sum_blocks<1, 1>(part_pq, nb_pq, tpq);
   double rz = tot[0][0], rr = tot[1][0];
   int it = s.it + 1;
   double rn = sqrt(rr);
@@ -782,6 +804,10 @@ __global__ __launch_bounds__(kBS) void k_cg_dir(int N, int k, const VT *__restri
     o.it = it;
     o.it_min = it_min;
     o.done = done;
+    // Later launches read the other parity slot, which still holds an older
+    // running state; the stop flag keeps them from updating x again.  Blocks
+    // of this launch that see it early skip only the direction update.
+    if (done) ctl->stop = 1;
   }
 }
 
@@ -794,8 +820,8 @@ __global__ __launch_bounds__(kBS) void k_w_spmv(int N, const int *__restrict__ r
                                                 const int *__restrict__ grp, const VT *__restrict__ p,
                                                 VT *__restrict__ q, const WarmCtl *ctl, double *part) {
   if (ctl->done) return;
-  spmv_partial<MT, VT, kGroups>(N, blockIdx.x * blockDim.x + threadIdx.x, rp, ci, val, D, cp, cc, cs, pblk, grp, p,
-                                q, part);
+  spmv_partial<MT, VT, kGroups>(N, (long)blockIdx.x * blockDim.x + threadIdx.x, rp, ci, val, D, cp, cc, cs, pblk,
+                                grp, p, q, part);
 }
 
 __global__ void k_w_alpha(int nbk, WarmCtl *ctl, const double *part) {
@@ -918,6 +944,7 @@ __global__ void k_cg_init_finish(int nbk, CgCtl *ctl, const double *part, double
     if (max_it <= 0) s.done = PCG_CAPPED;
     ctl->slot[1] = s;
     ctl->slot[1].it = -1;
+    ctl->stop = s.done ? 1 : 0;
   }
 }
 
@@ -990,9 +1017,9 @@ static int pcg_start(Scene &s, const double *rhs, double *xsol, bool start, doub
       hipLaunchKernelGGL(k_to_vt_f, dim3(blocks_for(n3, kBS)), dim3(kBS), 0, s.stream, xsol, (float *)p, n3);
     else
       hipLaunchKernelGGL(k_copy_d, dim3(blocks_for(n3, kBS)), dim3(kBS), 0, s.stream, xsol, (double *)p, n3);
-    hipLaunchKernelGGL((k_spmv<MT, VT>), dim3(nb), dim3(kBS), 0, s.stream, N, s.row_ptr.as<int>(), s.col_idx.as<int>(),
-                       val, D, s.coff_ptr.as<int>(), s.coff_col.as<int>(), s.coff_src.as<int>(), pblk, grp,
-                       NB > 1 ? 1 : 0, p, q);
+    hipLaunchKernelGGL((k_spmv<MT, VT>), dim3(blocks_for((long)N * kG, kBS)), dim3(kBS), 0, s.stream, N,
+                       s.row_ptr.as<int>(), s.col_idx.as<int>(), val, D, s.coff_ptr.as<int>(), s.coff_col.as<int>(),
+                       s.coff_src.as<int>(), pblk, grp, NB > 1 ? 1 : 0, p, q);
     use_q = true;
   }
   hipLaunchKernelGGL((k_pcg_init<MT, VT, NB>), dim3(nb), dim3(kBS), 0, s.stream, N, s.freev.as<uint8_t>(), Dinv, grp,
@@ -1000,12 +1027,57 @@ static int pcg_start(Scene &s, const double *rhs, double *xsol, bool start, doub
   return BAL_OK;
 }
 
+// Graph replay: a chunk of PCG iterations is captured once and replayed;
+// any change of a buffer address or size invalidates the capture.
+static bool graph_current(const std::vector<uintptr_t> &have, const std::vector<uintptr_t> &want,
+                          hipGraphExec_t exec) {
+  return exec != nullptr && have == want;
+}
+
+static void drop_graph(hipGraphExec_t &exec) {
+  if (exec) hipGraphExecDestroy(exec);
+  exec = nullptr;
+}
+
+template <typename F>
+static bool capture_graph(Scene &s, hipGraphExec_t &exec, F launches) {
+  drop_graph(exec);
+  if (hipStreamBeginCapture(s.stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  launches();
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(s.stream, &g);
+  if (e != hipSuccess || g == nullptr) {
+    (void)hipGetLastError();
+    if (g) hipGraphDestroy(g);
+    return false;
+  }
+  e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    exec = nullptr;
+    return false;
+  }
+  return true;
+}
+
+static void ensure_graph_events(Scene &s, int n) {
+  while ((int)s.graph_ev.size() < n) {
+    hipEvent_t e;
+    hipEventCreate(&e);
+    s.graph_ev.push_back(e);
+  }
+}
+
 template <typename MT, typename VT>
 static int cg_run(Scene &s, const double *rhs, double *xsol, double tol, double ref2, int max_iters, bool start,
                   bool resume, int *iters_out, double *rnorm_out) {
-  int N = s.N, nb = blocks_for(N, kBS);
-  if (s.partial.grow((size_t)nb * 6 * sizeof(double)) || s.pcg_ctl.grow(sizeof(CgCtl))) return BAL_E_OOM;
-  double *part_pq = s.partial.as<double>(), *part = part_pq + 3 * (size_t)nb;
+  int N = s.N, nb = blocks_for(N, kBS), nbs = blocks_for((long)N * kG, kBS);
+  if (s.partial.grow((size_t)(nbs + 3 * nb) * sizeof(double)) || s.pcg_ctl.grow(sizeof(CgCtl))) return BAL_E_OOM;
+  double *part_pq = s.partial.as<double>(), *part = part_pq + (size_t)nbs;
   CgCtl *ctl = s.pcg_ctl.as<CgCtl>();
   CgCtl *h = s.pin.as<CgCtl>();
   VT *p = static_cast<VT *>(s.pv.p), *q = static_cast<VT *>(s.q.p), *z = static_cast<VT *>(s.z.p);
@@ -1026,6 +1098,7 @@ static int cg_run(Scene &s, const double *rhs, double *xsol, double tol, double 
     h->slot[k & 1] = sl;
     h->max_it = k + max_iters;
     h->tol2 = 0.0;
+    h->stop = 0;
     hipMemcpyAsync(ctl, h, sizeof(CgCtl), hipMemcpyHostToDevice, s.stream);
   } else {
     pcg_start<MT, VT, 1>(s, rhs, xsol, start, part);
@@ -1034,21 +1107,59 @@ static int cg_run(Scene &s, const double *rhs, double *xsol, double tol, double 
     k = 0;
   }
   const int chunk = 16;
+  auto launch_iter = [&](int kk, hipEvent_t e0, hipEvent_t e1) {
+    if (e0) hipEventRecord(e0, s.stream);
+    hipLaunchKernelGGL((k_cg_spmv<MT, VT>), dim3(nbs), dim3(kBS), 0, s.stream, N, kk, s.row_ptr.as<int>(),
+                       s.col_idx.as<int>(), val, D, s.coff_ptr.as<int>(), s.coff_col.as<int>(), s.coff_src.as<int>(),
+                       pblk, p, q, ctl, part_pq);
+    if (e1) hipEventRecord(e1, s.stream);
+    hipLaunchKernelGGL((k_cg_update<MT, VT>), dim3(nb), dim3(kBS), 0, s.stream, N, kk, s.freev.as<uint8_t>(), Dinv, p,
+                       q, xsol, r, z, ctl, part_pq, nbs, part);
+    hipLaunchKernelGGL((k_cg_dir<VT>), dim3(nb), dim3(kBS), 0, s.stream, N, kk, z, p, ctl, part_pq, nbs, part);
+  };
+  // the kernels use only k & 1, so one capture serves every chunk that starts at an even k
+  std::vector<uintptr_t> sig = {(uintptr_t)s.row_ptr.p, (uintptr_t)s.col_idx.p, (uintptr_t)val, (uintptr_t)D,
+                                (uintptr_t)s.coff_ptr.p, (uintptr_t)s.coff_col.p, (uintptr_t)s.coff_src.p,
+                                (uintptr_t)pblk, (uintptr_t)p, (uintptr_t)q, (uintptr_t)ctl, (uintptr_t)part_pq,
+                                (uintptr_t)s.freev.p, (uintptr_t)Dinv, (uintptr_t)xsol, (uintptr_t)r, (uintptr_t)z,
+                                (uintptr_t)N, (uintptr_t)s.time_kernels};
   for (;;) {
-    for (int c = 0; c < chunk; ++c, ++k) {
-      hipEvent_t e0 = nullptr, e1 = nullptr;
-      if (s.time_kernels) { e0 = take_event(s); hipEventRecord(e0, s.stream); }
-      hipLaunchKernelGGL((k_cg_spmv<MT, VT>), dim3(nb), dim3(kBS), 0, s.stream, N, k, s.row_ptr.as<int>(),
-                         s.col_idx.as<int>(), val, D, s.coff_ptr.as<int>(), s.coff_col.as<int>(), s.coff_src.as<int>(),
-                         pblk, p, q, ctl, part_pq);
-      if (s.time_kernels) { e1 = take_event(s); hipEventRecord(e1, s.stream); }
-      hipLaunchKernelGGL((k_cg_update<MT, VT>), dim3(nb), dim3(kBS), 0, s.stream, N, k, s.freev.as<uint8_t>(), Dinv, p,
-                         q, xsol, r, z, ctl, part_pq, part);
-      hipLaunchKernelGGL((k_cg_dir<VT>), dim3(nb), dim3(kBS), 0, s.stream, N, k, z, p, ctl, part_pq, part);
+    bool graphed = false;
+    if (s.use_graphs && (k & 1) == 0) {
+      if (!graph_current(s.cg_sig, sig, s.cg_exec)) {
+        if (s.time_kernels) ensure_graph_events(s, 2 * chunk);
+        bool ok = capture_graph(s, s.cg_exec, [&]() {
+          for (int c = 0; c < chunk; ++c)
+            launch_iter(c, s.time_kernels ? s.graph_ev[2 * c] : nullptr, s.time_kernels ? s.graph_ev[2 * c + 1] : nullptr);
+        });
+        if (ok) s.cg_sig = sig; else { s.use_graphs = false; s.cg_sig.clear(); }
+      }
+      if (s.use_graphs && hipGraphLaunch(s.cg_exec, s.stream) == hipSuccess) graphed = true;
+    }
+    if (graphed) {
+      k += chunk;
+    } else {
+      for (int c = 0; c < chunk; ++c, ++k) {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (s.time_kernels) { e0 = take_event(s); e1 = take_event(s); }
+        launch_iter(k, e0, e1);
+      }
     }
     hipMemcpyAsync(h, ctl, sizeof(CgCtl), hipMemcpyDeviceToHost, s.stream);
     if (hipStreamSynchronize(s.stream) != hipSuccess) return BAL_E_HIP;
-    if (s.time_kernels) harvest_events(s);
+    if (s.time_kernels) {
+      if (graphed) {
+        for (int c = 0; c < chunk; ++c) {
+          float ms = 0.f;
+          if (hipEventElapsedTime(&ms, s.graph_ev[2 * c], s.graph_ev[2 * c + 1]) == hipSuccess) {
+            s.spmv_ms += ms;
+            s.spmv_launches += 1;
+          }
+        }
+      } else {
+        harvest_events(s);
+      }
+    }
     const CgSlot &sl = h->slot[h->slot[0].it >= h->slot[1].it ? 0 : 1];
     if (sl.done) {
       // SpMV launches after the stop exit at once; do not count them as timed work
@@ -1062,8 +1173,8 @@ static int cg_run(Scene &s, const double *rhs, double *xsol, double tol, double 
 
 template <typename MT, typename VT>
 static int warm_run(Scene &s, const double *rhs, double *xsol, double tol, int max_iters, int *iters_out) {
-  int N = s.N, nb = blocks_for(N, kBS);
-  if (s.partial.grow((size_t)nb * 3 * kGroups * sizeof(double)) || s.warm_ctl.grow(sizeof(WarmCtl))) return BAL_E_OOM;
+  int N = s.N, nb = blocks_for(N, kBS), nbs = blocks_for((long)N * kG, kBS);
+  if (s.partial.grow((size_t)nbs * 3 * kGroups * sizeof(double)) || s.warm_ctl.grow(sizeof(WarmCtl))) return BAL_E_OOM;
   double *part = s.partial.as<double>();
   WarmCtl *ctl = s.warm_ctl.as<WarmCtl>();
   VT *p = static_cast<VT *>(s.pv.p), *q = static_cast<VT *>(s.q.p), *z = static_cast<VT *>(s.z.p);
@@ -1075,17 +1186,34 @@ static int warm_run(Scene &s, const double *rhs, double *xsol, double tol, int m
   hipLaunchKernelGGL(k_w_init_finish, dim3(1), dim3(kBS), 0, s.stream, nb, ctl, part, tol * tol, max_iters);
   WarmCtl *h = s.pin.as<WarmCtl>();
   const int chunk = 8;
+  auto launch_iter = [&]() {
+    hipLaunchKernelGGL((k_w_spmv<MT, VT>), dim3(nbs), dim3(kBS), 0, s.stream, N, s.row_ptr.as<int>(),
+                       s.col_idx.as<int>(), val, D, s.coff_ptr.as<int>(), s.coff_col.as<int>(), s.coff_src.as<int>(),
+                       pblk, grp, p, q, ctl, part);
+    hipLaunchKernelGGL(k_w_alpha, dim3(1), dim3(kBS), 0, s.stream, nbs, ctl, part);
+    hipLaunchKernelGGL((k_w_update<MT, VT>), dim3(nb), dim3(kBS), 0, s.stream, N, s.freev.as<uint8_t>(), Dinv, grp, p,
+                       q, xsol, r, z, ctl, part);
+    hipLaunchKernelGGL(k_w_beta, dim3(1), dim3(kBS), 0, s.stream, nb, ctl, part);
+    hipLaunchKernelGGL((k_w_dir<VT>), dim3(nb), dim3(kBS), 0, s.stream, N, grp, z, p, ctl);
+  };
+  std::vector<uintptr_t> sig = {(uintptr_t)s.row_ptr.p, (uintptr_t)s.col_idx.p, (uintptr_t)val, (uintptr_t)D,
+                                (uintptr_t)s.coff_ptr.p, (uintptr_t)s.coff_col.p, (uintptr_t)s.coff_src.p,
+                                (uintptr_t)pblk, (uintptr_t)grp, (uintptr_t)p, (uintptr_t)q, (uintptr_t)ctl,
+                                (uintptr_t)part, (uintptr_t)s.freev.p, (uintptr_t)Dinv, (uintptr_t)xsol, (uintptr_t)r,
+                                (uintptr_t)z, (uintptr_t)N};
   for (;;) {
-    for (int c = 0; c < chunk; ++c) {
-      hipLaunchKernelGGL((k_w_spmv<MT, VT>), dim3(nb), dim3(kBS), 0, s.stream, N, s.row_ptr.as<int>(),
-                         s.col_idx.as<int>(), val, D, s.coff_ptr.as<int>(), s.coff_col.as<int>(), s.coff_src.as<int>(),
-                         pblk, grp, p, q, ctl, part);
-      hipLaunchKernelGGL(k_w_alpha, dim3(1), dim3(kBS), 0, s.stream, nb, ctl, part);
-      hipLaunchKernelGGL((k_w_update<MT, VT>), dim3(nb), dim3(kBS), 0, s.stream, N, s.freev.as<uint8_t>(), Dinv, grp, p,
-                         q, xsol, r, z, ctl, part);
-      hipLaunchKernelGGL(k_w_beta, dim3(1), dim3(kBS), 0, s.stream, nb, ctl, part);
-      hipLaunchKernelGGL((k_w_dir<VT>), dim3(nb), dim3(kBS), 0, s.stream, N, grp, z, p, ctl);
+    bool graphed = false;
+    if (s.use_graphs) {
+      if (!graph_current(s.warm_sig, sig, s.warm_exec)) {
+        bool ok = capture_graph(s, s.warm_exec, [&]() {
+          for (int c = 0; c < chunk; ++c) launch_iter();
+        });
+        if (ok) s.warm_sig = sig; else { s.use_graphs = false; s.warm_sig.clear(); }
+      }
+      if (s.use_graphs && hipGraphLaunch(s.warm_exec, s.stream) == hipSuccess) graphed = true;
     }
+    if (!graphed)
+      for (int c = 0; c < chunk; ++c) launch_iter();
     hipMemcpyAsync(h, ctl, sizeof(WarmCtl), hipMemcpyDeviceToHost, s.stream);
     if (hipStreamSynchronize(s.stream) != hipSuccess) return BAL_E_HIP;
     if (h->done) break;

@@ -1,0 +1,85 @@
+"""GPU adjoint: bal_step_adjoint against the oracle adjoint, and BalRollout
+gradients against central differences of whole rollouts."""
+import numpy as np
+import pytest
+
+import scenes
+from oracle import OracleScene, Params
+
+pytestmark = pytest.mark.gpu
+
+
+def small_beam(obstacle=False):
+    sc = scenes.beam(nx=6, ny=2, nz=2, cell=0.05, seed=0, n_steps=3)
+    if not obstacle:
+        sc["obs_pos"] = np.zeros((0, 3))
+        sc["obs_tris"] = np.zeros((0, 3), np.int32)
+    return sc
+
+
+def compare_adjoint(sc, n_pre, tol):
+    from paper_2407_00046_amd import Scene
+    g = Scene(sc, newton_rtol=1e-9, pcg_rtol=1e-12, max_newton=200)
+    o = OracleScene(sc, Params(newton_rtol=1e-9, max_newton=200))
+    for _ in range(n_pre):
+        g.step(allow=(0, -7))
+        o.step()
+    x_t, v_t = g.get_state()
+    n = o.n_body
+    assert np.abs(x_t - o.x[:n]).max() < 1e-6
+    st = o.step(return_state=True)
+    rng = np.random.default_rng(2)
+    w = rng.normal(size=(n, 3))
+    u = rng.normal(size=(n, 3))
+    gx_o, gv_o, gE_o = o.adjoint_step(o.x.copy(), st["y"], st["state"], w, u)
+    gE = np.zeros(len(sc["youngs"]))
+    gx, gv = g.step_adjoint(x_t, v_t, w, u, gE)
+    for a, b, name in ((gx, gx_o, "gx"), (gv, gv_o, "gv"), (gE, gE_o, "gE")):
+        err = np.abs(a - b).max() / np.abs(b).max()
+        print(f"{name}: rel err {err:.2e}")
+        assert err <= tol, name
+
+
+def test_adjoint_free_beam():
+    compare_adjoint(small_beam(), 1, 1e-6)
+
+
+def test_adjoint_with_contact():
+    """Tiny cube resting on the plane (barrier active, sigma set)."""
+    compare_adjoint(scenes.tiny_cube(), 2, 1e-5)
+
+
+def test_rollout_gradient_matches_central_differences():
+    import torch
+    from paper_2407_00046_amd import Scene
+    from paper_2407_00046_amd.bal import BalRollout
+    sc = small_beam()
+    g = Scene(sc, newton_rtol=1e-9, pcg_rtol=1e-12, max_newton=200)
+    T, every = 4, 2
+    n = sc["rest_pos"].shape[0]
+    tip = np.nonzero(np.abs(sc["rest_pos"][:, 0] - sc["rest_pos"][:, 0].max()) < 1e-9)[0]
+    target = torch.tensor(sc["rest_pos"][tip].mean(0) + np.array([0.0, -0.05, 0.0]))
+    E0 = torch.tensor(sc["youngs"], dtype=torch.float64, requires_grad=True)
+    v0 = torch.tensor(sc["v0"], dtype=torch.float64, requires_grad=True)
+
+    def loss_of(E, v):
+        xT = BalRollout.apply(E, v, g, sc["x0"], T, every)
+        return ((xT[tip].mean(0) - target) ** 2).sum()
+
+    L = loss_of(E0, v0)
+    L.backward()
+    rng = np.random.default_rng(1)
+    dlogE = torch.tensor(rng.normal(size=len(sc["youngs"])))
+    dv = torch.zeros_like(v0)
+    free = torch.tensor(sc["fixed"] == 0)
+    dv[free] = torch.tensor(rng.normal(size=(int(free.sum()), 3)))
+    with torch.no_grad():
+        an_E = float((E0.grad * E0 * dlogE).sum())
+        an_v = float((v0.grad * dv).sum())
+        eps = 1e-4
+        fd_E = (loss_of(E0 * torch.exp(eps * dlogE), v0) - loss_of(E0 * torch.exp(-eps * dlogE), v0)) / (2 * eps)
+        eps_v = 1e-3
+        fd_v = (loss_of(E0, v0 + eps_v * dv) - loss_of(E0, v0 - eps_v * dv)) / (2 * eps_v)
+    print(f"E: adjoint {an_E:.8e} fd {float(fd_E):.8e}; v0: adjoint {an_v:.8e} fd {float(fd_v):.8e}")
+    assert abs(an_E - float(fd_E)) <= 1e-4 * abs(float(fd_E))
+    assert abs(an_v - float(fd_v)) <= 1e-4 * abs(float(fd_v))
