@@ -33,12 +33,16 @@ HBM_PEAK_GBS = 8000.0
 
 
 def run_precision(sc, precision, steps, warmup, stream):
+    """Times `steps` steps after `warmup` steps (PCG replayed as HIP graphs),
+    then replays the same steps from the same state with kernel timing on
+    (every PCG SpMV bracketed by HIP events on the scene's stream) for the
+    SpMV roofline."""
     import torch
     from paper_2407_00046_amd import Scene
     g = Scene(sc, precision=precision, newton_rtol=1e-4, pcg_rtol=1e-4, device=0, stream=stream)
     for _ in range(warmup):
         g.step(allow=(0, -7))
-    g.set_kernel_timing(True)
+    x_w, v_w = g.get_state()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     stats = []
@@ -46,12 +50,17 @@ def run_precision(sc, precision, steps, warmup, stream):
         stats.append(g.step(allow=(0, -7)))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    x_end, _ = g.get_state()
+    g.set_state(x_w, v_w)
+    g.set_kernel_timing(True)
+    timed = [g.step(allow=(0, -7)) for _ in range(steps)]
+    g.set_kernel_timing(False)
     newton = sum(s["newton_iters"] for s in stats)
     pcg = sum(s["pcg_iters"] for s in stats)
     warm = sum(s["warm_iters"] for s in stats)
     sec_pcg = sum(s["sec_pcg"] for s in stats)
-    spmv_ms = sum(s["spmv_ms"] for s in stats)
-    spmv_n = sum(s["spmv_launches"] for s in stats)
+    spmv_ms = sum(s["spmv_ms"] for s in timed)
+    spmv_n = sum(s["spmv_launches"] for s in timed)
     out = dict(
         s_per_step=wall / steps,
         newton_iters_per_step=newton / steps,
@@ -63,17 +72,58 @@ def run_precision(sc, precision, steps, warmup, stream):
         sec_ccd_per_step=sum(s["sec_ccd"] for s in stats) / steps,
         sec_collision_per_step=sum(s["sec_collision"] for s in stats) / steps,
         sec_linesearch_per_step=sum(s["sec_linesearch"] for s in stats) / steps,
+        graph_launches_per_step=sum(s["graph_launches"] for s in stats) / steps,
         n_active_max=max(s["n_active_max"] for s in stats),
         converged_steps=sum(s["converged"] for s in stats),
+        timed_replay_same_iters=[s["pcg_iters"] for s in timed] == [s["pcg_iters"] for s in stats],
         spmv_launches=spmv_n,
-        spmv_ms_avg=spmv_ms / spmv_n if spmv_n else None,
-        spmv_bytes=stats[-1]["spmv_bytes"],
+        spmv_ms_avg=spmv_ms / spmv_n if spmv_n > 0 else None,
+        spmv_bytes=timed[-1]["spmv_bytes"],
     )
-    if spmv_n:
+    if spmv_n > 0 and spmv_ms > 0:
         out["spmv_gbs"] = out["spmv_bytes"] / (out["spmv_ms_avg"] * 1e-3) / 1e9
-    x, _ = g.get_state()
     g.close()
-    return out, x
+    return out, x_end
+
+
+def copy_peak_gbs(stream, mib=2048, reps=20):
+    """Streaming-copy bandwidth (read + write bytes) of a device-to-device copy."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * n * 4 / (ms * 1e-3) / 1e9
+
+
+def spmv_r1(stream, n=128, reps=50):
+    """Block SpMV on the 128^3-cell grid (2.1M nodes, 12.7M off-diagonal block
+    pairs): large enough that the matrix does not fit the on-chip caches, so
+    the figure is an HBM figure.  Values are Neo-Hookean Hessians at a
+    randomly perturbed state plus M/h^2."""
+    import scenes
+    from paper_2407_00046_amd import Scene
+    sc = scenes.spmv_grid(n)
+    x = np.asarray(sc["x0"])
+    out = {"workload": sc["name"], "n_nodes": int(x.shape[0]), "n_tets": int(sc["tets"].shape[0])}
+    for prec in ("mixed", "fp64"):
+        g = Scene(sc, precision=prec, device=0, stream=stream)
+        g.linearize(x, sigma=0.0)
+        ms, by = g.spmv_benchmark(reps=reps)
+        g.close()
+        out[prec] = dict(ms_per_launch=ms, bytes_per_launch=by, gbs=by / (ms * 1e-3) / 1e9,
+                         frac=by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS)
+        print(f"[bench] spmv {sc['name']} {prec}: {ms * 1e3:.1f} us, {out[prec]['gbs']:.0f} GB/s", flush=True)
+    return out
 
 
 def cpu_baseline(sc, gpu_newton_per_step):
@@ -96,6 +146,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cells", type=int, default=16)
+    ap.add_argument("--no-r1", action="store_true", help="skip the 128^3-grid SpMV roofline")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding of this path is a "
@@ -116,6 +167,11 @@ def main():
         print(f"[bench] fp64: {fp64['s_per_step']:.3f} s/step", flush=True)
         L = np.linalg.norm(sc["x0"].max(0) - sc["x0"].min(0))
         mixed["eps_x_vs_fp64"] = float(np.linalg.norm(xm - xf, axis=1).max() / L)
+    r1 = None
+    if not args.no_r1:
+        r1 = spmv_r1(stream)
+        r1["copy_peak_gbs"] = copy_peak_gbs(stream)
+        print(f"[bench] streaming copy: {r1['copy_peak_gbs']:.0f} GB/s", flush=True)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(sc, mixed["newton_iters_per_step"])
@@ -124,7 +180,7 @@ def main():
     roof = None
     if ach:
         roof = dict(bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS, traffic=None,
-                    kernel="k_pcg_spmv<float,float,1>", bytes_per_launch=mixed["spmv_bytes"],
+                    kernel="k_cg_spmv<float,float>", bytes_per_launch=mixed["spmv_bytes"],
                     avg_launch_ms=mixed["spmv_ms_avg"])
     line = dict(
         metric="s/timestep & PCG iters/s, mixed vs FP64 at 1e-4 tol; BSR SpMV HBM GB/s",
@@ -133,7 +189,7 @@ def main():
         dtype="mixed f32/f64", data="synthetic",
         config=dict(workload=sc["name"], n_tets=int(sc["tets"].shape[0]), n_verts=int(sc["rest_pos"].shape[0]),
                     precision="mixed", dt=sc["dt"], dhat=sc["dhat"], newton_rtol=1e-4, pcg_rtol=1e-4),
-        roofline=roof, cpu_baseline=cpu, mixed=mixed, fp64=fp64,
+        roofline=roof, cpu_baseline=cpu, spmv_hbm=r1, mixed=mixed, fp64=fp64,
     )
     print(json.dumps(line), flush=True)
 

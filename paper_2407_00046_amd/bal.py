@@ -48,7 +48,8 @@ class bal_step_stats(C.Structure):
     _fields_ = [
         ("newton_iters", C.c_int32), ("pcg_iters", C.c_int32), ("warm_iters", C.c_int32),
         ("n_active_max", C.c_int32), ("n_aug_max", C.c_int32), ("converged", C.c_int32),
-        ("ls_retries", C.c_int32), ("spmv_launches", C.c_int32),
+        ("ls_retries", C.c_int32), ("spmv_launches", C.c_int32), ("graph_launches", C.c_int32),
+        ("reserved", C.c_int32),
         ("sigma", C.c_double), ("min_dist", C.c_double), ("sec_total", C.c_double), ("sec_pcg", C.c_double),
         ("sec_hessian", C.c_double), ("sec_ccd", C.c_double), ("sec_collision", C.c_double),
         ("sec_linesearch", C.c_double), ("spmv_ms", C.c_double), ("spmv_bytes", C.c_double),

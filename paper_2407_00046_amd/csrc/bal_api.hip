@@ -349,6 +349,7 @@ static int newton_solve(Scene &s, bal_step_stats *st, bool record) {
   bal_step_stats S{};
   s.spmv_ms = 0.0;
   s.spmv_launches = 0;
+  s.graph_launches = 0;
   auto tc = clk::now();
   int rc = build_candidates(s, s.cand, x, nullptr);
   if (rc) return rc;
@@ -475,6 +476,7 @@ static int newton_solve(Scene &s, bal_step_stats *st, bool record) {
   S.sigma = s.sigma_set ? s.sigma : 0.0;
   S.spmv_ms = s.spmv_ms;
   S.spmv_launches = s.spmv_launches;
+  S.graph_launches = s.graph_launches;
   S.spmv_bytes = spmv_bytes(s);
   if ((rc = sync(s))) return rc;
   S.sec_total = since(t_start);
@@ -679,7 +681,8 @@ static int build_scene(Scene &s, const bal_scene_desc *d) {
   }
   s.cell = cnt ? elen / cnt : 1.0;
   if (s.cell < 4.0 * d->dhat) s.cell = 4.0 * d->dhat;
-  // full block pattern over free nodes with element sources
+  // strictly lower block pattern over free nodes with element sources; the
+  // upper triangle is read through the transposed index built below
   std::vector<int> rp(N + 1, 0), ci, bsp(1, 0), bsrc;
   {
     std::vector<std::pair<int, int>> ent;
@@ -692,7 +695,7 @@ static int build_scene(Scene &s, const bal_scene_desc *d) {
           for (int b = 0; b < 4; ++b) {
             if (b == a) continue;
             int j = v[b];
-            if (!s.free_h[j]) continue;
+            if (j >= i || !s.free_h[j]) continue;
             int src = a < b ? (10 * t + slot_of(a, b)) : (int)((unsigned)(10 * t + slot_of(b, a)) | 0x80000000u);
             ent.push_back({j, src});
           }
@@ -712,6 +715,16 @@ static int build_scene(Scene &s, const bal_scene_desc *d) {
   }
   s.nnzb = (int)ci.size();
   s.nsrc = (int)bsrc.size();
+  // transposed index: row j lists the stored blocks (i, j), ascending i
+  std::vector<int> upp(N + 1, 0);
+  std::vector<int2> upe(std::max(s.nnzb, 1));
+  for (int k = 0; k < s.nnzb; ++k) upp[ci[k] + 1]++;
+  for (int i = 0; i < N; ++i) upp[i + 1] += upp[i];
+  {
+    std::vector<int> fill(upp.begin(), upp.end() - 1);
+    for (int i = 0; i < N; ++i)
+      for (int k = rp[i]; k < rp[i + 1]; ++k) upe[fill[ci[k]]++] = make_int2(i, k);
+  }
   // device uploads
   std::vector<int4> tet4(T);
   for (int t = 0; t < T; ++t) tet4[t] = make_int4(d->tets[4 * t], d->tets[4 * t + 1], d->tets[4 * t + 2], d->tets[4 * t + 3]);
@@ -721,6 +734,7 @@ static int build_scene(Scene &s, const bal_scene_desc *d) {
       (rc = upload(s, s.node_tet_ptr, ntp.data(), N + 1)) || (rc = upload(s, s.node_tet_src, nts.data(), nts.size())) ||
       (rc = upload(s, s.row_ptr, rp.data(), N + 1)) || (rc = upload(s, s.col_idx, ci.data(), ci.size())) ||
       (rc = upload(s, s.blk_src_ptr, bsp.data(), bsp.size())) || (rc = upload(s, s.blk_src, bsrc.data(), bsrc.size())) ||
+      (rc = upload(s, s.up_ptr, upp.data(), N + 1)) || (rc = upload(s, s.up_ent, upe.data(), upe.size())) ||
       (rc = upload(s, s.sv, s.sv_h.data(), s.sv_h.size())) || (rc = upload(s, s.st, s.st_h.data(), s.st_h.size())) ||
       (rc = upload(s, s.se, s.se_h.data(), s.se_h.size())))
     return rc;
@@ -843,7 +857,7 @@ void bal_destroy_scene(bal_scene *h) {
   hipSetDevice(s.dev);
   hipStreamSynchronize(s.stream);
   DBuf *bufs[] = {&s.tets, &s.tc, &s.mass, &s.freev, &s.node_tet_ptr, &s.node_tet_src, &s.row_ptr, &s.col_idx,
-                  &s.blk_src_ptr, &s.blk_src, &s.row_of, &s.sv, &s.st, &s.se, &s.x, &s.v, &s.x_t, &s.v_t, &s.y,
+                  &s.blk_src_ptr, &s.blk_src, &s.up_ptr, &s.up_ent, &s.sv, &s.st, &s.se, &s.x, &s.v, &s.x_t, &s.v_t, &s.y,
                   &s.xtrial, &s.dx, &s.tet_e, &s.tet_g, &s.tet_tr, &s.tet_blk, &s.val, &s.Dblk, &s.Dinv, &s.e_nodes,
                   &s.group, &s.grad, &s.grad_b, &s.uni_flag, &s.uni_aug, &s.pair_e, &s.pair_g, &s.pair_tr,
                   &s.pair_blk, &s.cdiag_ptr, &s.cdiag_src, &s.coff_ptr, &s.coff_col, &s.coff_src, &s.ccount,
@@ -861,7 +875,6 @@ void bal_destroy_scene(bal_scene *h) {
   }
   if (s.pin.p) hipHostFree(s.pin.p);
   for (hipEvent_t e : s.ev_pool) hipEventDestroy(e);
-  for (hipEvent_t e : s.graph_ev) hipEventDestroy(e);
   if (s.cg_exec) hipGraphExecDestroy(s.cg_exec);
   if (s.warm_exec) hipGraphExecDestroy(s.warm_exec);
   if (s.own_stream && s.stream) hipStreamDestroy(s.stream);

@@ -47,9 +47,10 @@ struct Scene {
   std::vector<int> sv_h, st_h, se_h;
   std::vector<double> youngs_h, poisson_h;
   // static device data
-  DBuf tets, tc, mass, freev, node_tet_ptr, node_tet_src, row_ptr, col_idx, blk_src_ptr, blk_src, row_of;
+  DBuf tets, tc, mass, freev, node_tet_ptr, node_tet_src, row_ptr, col_idx, blk_src_ptr, blk_src;
+  DBuf up_ptr, up_ent;   // per row j: (i, block index) of the stored blocks (i, j), i > j, ascending i
   DBuf sv, st, se;
-  int nnzb = 0;          // off-diagonal blocks of the full (both triangles) pattern
+  int nnzb = 0;          // stored off-diagonal element blocks: strictly lower triangle (i > j)
   int nsrc = 0;
   // state
   DBuf x, v, x_t, v_t, y, xtrial, dx;
@@ -82,13 +83,13 @@ struct Scene {
   bool own_stream = false;
   hipGraphExec_t cg_exec = nullptr, warm_exec = nullptr;
   std::vector<uintptr_t> cg_sig, warm_sig;
-  std::vector<hipEvent_t> graph_ev;
   // timing
   bool time_kernels = false;
   std::vector<hipEvent_t> ev_pool;
   int ev_used = 0;
   double spmv_ms = 0.0;
   int spmv_launches = 0;
+  int graph_launches = 0;
   // trace of the last step
   std::vector<double> trace;
   bool linearized = false;

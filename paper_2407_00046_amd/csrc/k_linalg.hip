@@ -2,13 +2,15 @@
 // block-Jacobi warm start, App. B stopping rules), plus deterministic
 // reductions and scans.
 //
-// Storage.  The static element part is a full (both triangles) 3x3 block
-// CSR over free nodes, gathered per block from per-tet blocks through a
-// static source list, so assembly and SpMV need no atomics and are
-// bit-reproducible.  Contact blocks stay in per-pair buffers; per Newton
+// Storage.  The static element part is the strictly lower triangle of a 3x3
+// block CSR over free nodes (plus a transposed index for the upper half),
+// gathered per block from per-tet blocks through a static source list, so
+// assembly and SpMV need no atomics and are bit-reproducible.  Contact blocks stay in per-pair buffers; per Newton
 // iteration each row gets a sorted list of the contact blocks it reads.
 // Diagonal blocks (mass + elements + contacts) form the dense block
 // diagonal D that also feeds the block-Jacobi preconditioner.
+#include <hip/hip_ext.h>
+
 #include <algorithm>
 
 #include "bal_internal.h"
@@ -484,70 +486,110 @@ void launch_offdiag_assembly(Scene &s) {
 }
 
 // ---------------------------------------------------------------- SpMV
-// y_i = D_i v_i + sum_static A_ij v_j + sum_contact C_ij v_j; with masked,
-// blocks whose row and column lie in different stiffness groups are skipped
-// (the warm start's domain-decomposed product, Sec. 4.2).
-// One block row computed by a group of kG consecutive lanes: lane g of the
-// group takes blocks g, g + kG, ... of the row (static and contact parts),
-// the partial products are summed with shuffles, and lane 0 of the group
-// adds D_i v_i and holds the result.  Consecutive lanes read consecutive
-// 36/72-byte blocks of the row, and a 39K-row system fills kG times as
-// many waves as one thread per row would.
+// y_i = D_i v_i + sum_{j<i} L_ij v_j + sum_{m>i} L_mi^T v_m + sum_contact C_ij v_j.
+// The element part is stored once, as its strictly lower triangle L (block
+// CSR by row, the paper's symmetric storage, Sec. 5.1); row i reads its own
+// blocks directly and the blocks of column i through the transposed index
+// (row m, block position), so every block is fetched from HBM once and its
+// second use is served from cache.  Row-gather only: no atomics, and the
+// summation order is fixed.  With masked, blocks whose row and column lie in
+// different stiffness groups are skipped (the warm start's domain-decomposed
+// product, Sec. 4.2).
+// One block row is computed by a group of kG consecutive lanes: lane g takes
+// entries g, g + kG, ... of the row's concatenated lower and transposed lists
+// (then of its contact list), partial products are summed with shuffles, and
+// lane 0 of the group adds D_i v_i and holds the result.
 constexpr int kG = 4;
 
+template <typename MT>
+struct BsrView {
+  const int *rp, *ci;   // lower rows: row_ptr, column
+  const MT *val;        // 9 scalars per stored block
+  const int *up;        // transposed rows: pointer
+  const int2 *ue;       // (row m, block position) of the blocks (m, j), m > j
+  const MT *D;          // diagonal blocks
+  const int *cp, *cc, *cs;  // contact rows: pointer, column, pair-block source
+  const MT *pblk;
+};
+
+template <typename MT>
+static BsrView<MT> bsr_view(const Scene &s) {
+  return BsrView<MT>{s.row_ptr.as<int>(), s.col_idx.as<int>(), static_cast<const MT *>(s.val.p), s.up_ptr.as<int>(),
+                     s.up_ent.as<int2>(), static_cast<const MT *>(s.Dblk.p), s.coff_ptr.as<int>(),
+                     s.coff_col.as<int>(), s.coff_src.as<int>(), static_cast<const MT *>(s.pair_blk.p)};
+}
+
+template <typename MT>
+static std::vector<uintptr_t> bsr_sig(const BsrView<MT> &B) {
+  return {(uintptr_t)B.rp, (uintptr_t)B.ci, (uintptr_t)B.val, (uintptr_t)B.up, (uintptr_t)B.ue, (uintptr_t)B.D,
+          (uintptr_t)B.cp, (uintptr_t)B.cc, (uintptr_t)B.cs, (uintptr_t)B.pblk};
+}
+
+// Workgroups are handed to the 8 XCDs round-robin; this permutation gives
+// each XCD one contiguous range of tiles, so that the rows sharing a block or
+// a vector entry mostly run on the same XCD and meet in its L2.  The grid
+// must be a multiple of 8 (spmv_grid).
+__device__ __forceinline__ int xcd_tile() {
+  return (int)((blockIdx.x & 7u) * (gridDim.x >> 3) + (blockIdx.x >> 3));
+}
+inline int spmv_grid(int N) {
+  int nb = blocks_for((long)N * kG, kBS);
+  return (nb + 7) & ~7;
+}
+
 template <typename MT, typename VT>
-__device__ __forceinline__ void spmv_row(int i, int g, const int *__restrict__ rp, const int *__restrict__ ci,
-                                         const MT *__restrict__ val, const MT *__restrict__ D,
-                                         const int *__restrict__ cp, const int *__restrict__ cc,
-                                         const int *__restrict__ cs, const MT *__restrict__ pblk,
-                                         const int *__restrict__ grp, int masked, const VT *__restrict__ v,
-                                         VT *acc) {
+__device__ __forceinline__ void blk_mv(const MT *__restrict__ a, const VT *__restrict__ v, int j, VT *acc) {
+  VT w0 = v[3 * j], w1 = v[3 * j + 1], w2 = v[3 * j + 2];
+  acc[0] += (VT)a[0] * w0 + (VT)a[1] * w1 + (VT)a[2] * w2;
+  acc[1] += (VT)a[3] * w0 + (VT)a[4] * w1 + (VT)a[5] * w2;
+  acc[2] += (VT)a[6] * w0 + (VT)a[7] * w1 + (VT)a[8] * w2;
+}
+template <typename MT, typename VT>
+__device__ __forceinline__ void blk_mtv(const MT *__restrict__ a, const VT *__restrict__ v, int j, VT *acc) {
+  VT w0 = v[3 * j], w1 = v[3 * j + 1], w2 = v[3 * j + 2];
+  acc[0] += (VT)a[0] * w0 + (VT)a[3] * w1 + (VT)a[6] * w2;
+  acc[1] += (VT)a[1] * w0 + (VT)a[4] * w1 + (VT)a[7] * w2;
+  acc[2] += (VT)a[2] * w0 + (VT)a[5] * w1 + (VT)a[8] * w2;
+}
+
+template <typename MT, typename VT>
+__device__ __forceinline__ void spmv_row(int i, int g, const BsrView<MT> &B, const int *__restrict__ grp, int masked,
+                                         const VT *__restrict__ v, VT *acc) {
   acc[0] = acc[1] = acc[2] = (VT)0;
   if (i >= 0) {
     int gi = masked ? grp[i] : 0;
-    for (int k = rp[i] + g; k < rp[i + 1]; k += kG) {
-      int j = ci[k];
-      if (masked && grp[j] != gi) continue;
-      const MT *a = val + (size_t)9 * k;
-      VT w0 = v[3 * j], w1 = v[3 * j + 1], w2 = v[3 * j + 2];
-      acc[0] += (VT)a[0] * w0 + (VT)a[1] * w1 + (VT)a[2] * w2;
-      acc[1] += (VT)a[3] * w0 + (VT)a[4] * w1 + (VT)a[5] * w2;
-      acc[2] += (VT)a[6] * w0 + (VT)a[7] * w1 + (VT)a[8] * w2;
+    const int l0 = B.rp[i], nl = B.rp[i + 1] - l0, u0 = B.up[i], nt = nl + (B.up[i + 1] - u0);
+    for (int t = g; t < nt; t += kG) {
+      if (t < nl) {
+        int k = l0 + t, j = B.ci[k];
+        if (masked && grp[j] != gi) continue;
+        blk_mv<MT, VT>(B.val + (size_t)9 * k, v, j, acc);
+      } else {
+        int2 e = B.ue[u0 + t - nl];
+        if (masked && grp[e.x] != gi) continue;
+        blk_mtv<MT, VT>(B.val + (size_t)9 * e.y, v, e.x, acc);
+      }
     }
-    for (int k = cp[i] + g; k < cp[i + 1]; k += kG) {
-      int j = cc[k];
+    for (int k = B.cp[i] + g; k < B.cp[i + 1]; k += kG) {
+      int j = B.cc[k];
       if (masked && grp[j] != gi) continue;
-      const MT *a = pblk + (size_t)9 * cs[k];
-      VT w0 = v[3 * j], w1 = v[3 * j + 1], w2 = v[3 * j + 2];
-      acc[0] += (VT)a[0] * w0 + (VT)a[1] * w1 + (VT)a[2] * w2;
-      acc[1] += (VT)a[3] * w0 + (VT)a[4] * w1 + (VT)a[5] * w2;
-      acc[2] += (VT)a[6] * w0 + (VT)a[7] * w1 + (VT)a[8] * w2;
+      blk_mv<MT, VT>(B.pblk + (size_t)9 * B.cs[k], v, j, acc);
     }
   }
 #pragma unroll
   for (int o = kG / 2; o > 0; o >>= 1)
 #pragma unroll
     for (int c = 0; c < 3; ++c) acc[c] += __shfl_xor(acc[c], o, kG);
-  if (i >= 0 && g == 0) {
-    VT v0 = v[3 * i], v1 = v[3 * i + 1], v2 = v[3 * i + 2];
-    const MT *d = D + (size_t)9 * i;
-    acc[0] += (VT)d[0] * v0 + (VT)d[1] * v1 + (VT)d[2] * v2;
-    acc[1] += (VT)d[3] * v0 + (VT)d[4] * v1 + (VT)d[5] * v2;
-    acc[2] += (VT)d[6] * v0 + (VT)d[7] * v1 + (VT)d[8] * v2;
-  }
+  if (i >= 0 && g == 0) blk_mv<MT, VT>(B.D + (size_t)9 * i, v, i, acc);
 }
 
 template <typename MT, typename VT>
-__global__ __launch_bounds__(kBS) void k_spmv(int N, const int *__restrict__ rp, const int *__restrict__ ci,
-                                              const MT *__restrict__ val, const MT *__restrict__ D,
-                                              const int *__restrict__ cp, const int *__restrict__ cc,
-                                              const int *__restrict__ cs, const MT *__restrict__ pblk,
-                                              const int *__restrict__ grp, int masked, const VT *__restrict__ v,
-                                              VT *__restrict__ out) {
-  long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(kBS) void k_spmv(int N, BsrView<MT> B, const int *__restrict__ grp, int masked,
+                                              const VT *__restrict__ v, VT *__restrict__ out) {
+  long t = (long)xcd_tile() * blockDim.x + threadIdx.x;
   int i = (int)(t / kG), g = (int)(t % kG);
   VT acc[3];
-  spmv_row<MT, VT>(i < N ? i : -1, g, rp, ci, val, D, cp, cc, cs, pblk, grp, masked, v, acc);
+  spmv_row<MT, VT>(i < N ? i : -1, g, B, grp, masked, v, acc);
   if (i < N && g == 0) {
     out[3 * i] = acc[0];
     out[3 * i + 1] = acc[1];
@@ -556,23 +598,19 @@ __global__ __launch_bounds__(kBS) void k_spmv(int N, const int *__restrict__ rp,
 }
 
 void launch_spmv(Scene &s, const void *vin, void *vout, int masked) {
-  dim3 g(blocks_for((long)s.N * kG, kBS)), b(kBS);
+  dim3 g(spmv_grid(s.N)), b(kBS);
   if (s.mixed)
-    hipLaunchKernelGGL((k_spmv<float, float>), g, b, 0, s.stream, s.N, s.row_ptr.as<int>(), s.col_idx.as<int>(),
-                       s.val.as<float>(), s.Dblk.as<float>(), s.coff_ptr.as<int>(), s.coff_col.as<int>(),
-                       s.coff_src.as<int>(), s.pair_blk.as<float>(), s.group.as<int>(), masked,
+    hipLaunchKernelGGL((k_spmv<float, float>), g, b, 0, s.stream, s.N, bsr_view<float>(s), s.group.as<int>(), masked,
                        static_cast<const float *>(vin), static_cast<float *>(vout));
   else
-    hipLaunchKernelGGL((k_spmv<double, double>), g, b, 0, s.stream, s.N, s.row_ptr.as<int>(), s.col_idx.as<int>(),
-                       s.val.as<double>(), s.Dblk.as<double>(), s.coff_ptr.as<int>(), s.coff_col.as<int>(),
-                       s.coff_src.as<int>(), s.pair_blk.as<double>(), s.group.as<int>(), masked,
-                       static_cast<const double *>(vin), static_cast<double *>(vout));
+    hipLaunchKernelGGL((k_spmv<double, double>), g, b, 0, s.stream, s.N, bsr_view<double>(s), s.group.as<int>(),
+                       masked, static_cast<const double *>(vin), static_cast<double *>(vout));
 }
 
 double spmv_bytes(const Scene &s) {
   // the paper's symmetric storage: each off-diagonal pair of blocks once
   double w = s.mixed ? 4.0 : 8.0;
-  double nL = 0.5 * (double)s.nnzb, nC = 0.5 * (double)s.n_coff;
+  double nL = (double)s.nnzb, nC = 0.5 * (double)s.n_coff;
   double N = (double)s.N;
   return (nL + nC) * (9.0 * w + 4.0) + N * 9.0 * w + 4.0 * N + 3.0 * N * w + 3.0 * N * w;
 }
@@ -620,9 +658,9 @@ __device__ __forceinline__ void wave_bin_sums(int bin, double v, double *wave_ou
   }
 }
 
-// Block per-bin sums written to part[(v * nbk + block) * NB + bin].
+// Block per-bin sums written to part[(v * nbk + blk) * NB + bin], nbk = gridDim.x.
 template <int NB, int NV>
-__device__ void block_partials(int bin, const double *vals, double *part) {
+__device__ void block_partials(int bin, const double *vals, double *part, int blk) {
   constexpr int W = kBS / 64;
   __shared__ double wsum[W][NV][NB];
   const int w = threadIdx.x >> 6;
@@ -648,7 +686,7 @@ __device__ void block_partials(int bin, const double *vals, double *part) {
 #pragma unroll
     for (int q = 0; q < W; ++q) acc += (&wsum[q][0][0])[k];
     int v = k / NB, b = k % NB;
-    part[((size_t)v * nbk + blockIdx.x) * NB + b] = acc;
+    part[((size_t)v * nbk + blk) * NB + b] = acc;
   }
 }
 
@@ -689,14 +727,15 @@ struct WarmCtl {
 
 // ---- shared pieces
 template <typename MT, typename VT, int NB>
-__device__ __forceinline__ void spmv_partial(int N, long t, const int *rp, const int *ci, const MT *val, const MT *D,
-                                             const int *cp, const int *cc, const int *cs, const MT *pblk,
-                                             const int *grp, const VT *p, VT *q, double *part) {
+__device__ __forceinline__ void spmv_partial(int N, const BsrView<MT> &B, const int *grp, const VT *p, VT *q,
+                                             double *part) {
+  const int tile = xcd_tile();
+  long t = (long)tile * blockDim.x + threadIdx.x;
   double vals[1] = {0.0};
   int bin = -1;
   int i = (int)(t / kG), g = (int)(t % kG);
   VT acc[3];
-  spmv_row<MT, VT>(i < N ? i : -1, g, rp, ci, val, D, cp, cc, cs, pblk, grp, NB > 1, p, acc);
+  spmv_row<MT, VT>(i < N ? i : -1, g, B, grp, NB > 1, p, acc);
   if (i < N && g == 0) {
     q[3 * i] = acc[0];
     q[3 * i + 1] = acc[1];
@@ -705,7 +744,7 @@ __device__ __forceinline__ void spmv_partial(int N, long t, const int *rp, const
     vals[0] = (double)p[3 * i] * (double)acc[0] + (double)p[3 * i + 1] * (double)acc[1] +
               (double)p[3 * i + 2] * (double)acc[2];
   }
-  block_partials<NB, 1>(bin, vals, part);
+  block_partials<NB, 1>(bin, vals, part, tile);
 }
 
 // x += al p ; r -= al q ; z = Dinv r ; partial r.z and r.r
@@ -736,20 +775,15 @@ __device__ __forceinline__ void update_partial(int N, int i, const uint8_t *fr, 
       vals[1] += rr[c] * rr[c];
     }
   }
-  block_partials<NB, 2>(bin, vals, part);
+  block_partials<NB, 2>(bin, vals, part, blockIdx.x);
 }
 
 // ---- global solve
 template <typename MT, typename VT>
-__global__ __launch_bounds__(kBS) void k_cg_spmv(int N, int k, const int *__restrict__ rp, const int *__restrict__ ci,
-                                                 const MT *__restrict__ val, const MT *__restrict__ D,
-                                                 const int *__restrict__ cp, const int *__restrict__ cc,
-                                                 const int *__restrict__ cs, const MT *__restrict__ pblk,
-                                                 const VT *__restrict__ p, VT *__restrict__ q, const CgCtl *ctl,
-                                                 double *part) {
+__global__ __launch_bounds__(kBS) void k_cg_spmv(int N, int k, BsrView<MT> B, const VT *__restrict__ p,
+                                                 VT *__restrict__ q, const CgCtl *ctl, double *part) {
   if (ctl->stop || ctl->slot[k & 1].done) return;
-  spmv_partial<MT, VT, 1>(N, (long)blockIdx.x * blockDim.x + threadIdx.x, rp, ci, val, D, cp, cc, cs, pblk, nullptr, p,
-                          q, part);
+  spmv_partial<MT, VT, 1>(N, B, nullptr, p, q, part);
 }
 
 template <typename MT, typename VT>
@@ -813,15 +847,11 @@ __global__ __launch_bounds__(kBS) void k_cg_dir(int N, int k, const VT *__restri
 
 // ---- warm start (per-group bins)
 template <typename MT, typename VT>
-__global__ __launch_bounds__(kBS) void k_w_spmv(int N, const int *__restrict__ rp, const int *__restrict__ ci,
-                                                const MT *__restrict__ val, const MT *__restrict__ D,
-                                                const int *__restrict__ cp, const int *__restrict__ cc,
-                                                const int *__restrict__ cs, const MT *__restrict__ pblk,
-                                                const int *__restrict__ grp, const VT *__restrict__ p,
-                                                VT *__restrict__ q, const WarmCtl *ctl, double *part) {
+__global__ __launch_bounds__(kBS) void k_w_spmv(int N, BsrView<MT> B, const int *__restrict__ grp,
+                                                const VT *__restrict__ p, VT *__restrict__ q, const WarmCtl *ctl,
+                                                double *part) {
   if (ctl->done) return;
-  spmv_partial<MT, VT, kGroups>(N, (long)blockIdx.x * blockDim.x + threadIdx.x, rp, ci, val, D, cp, cc, cs, pblk,
-                                grp, p, q, part);
+  spmv_partial<MT, VT, kGroups>(N, B, grp, p, q, part);
 }
 
 __global__ void k_w_alpha(int nbk, WarmCtl *ctl, const double *part) {
@@ -920,7 +950,7 @@ __global__ __launch_bounds__(kBS) void k_pcg_init(int N, const uint8_t *__restri
       }
     }
   }
-  block_partials<NB, 3>(bin, vals, part);
+  block_partials<NB, 3>(bin, vals, part, blockIdx.x);
 }
 
 __global__ void k_cg_init_finish(int nbk, CgCtl *ctl, const double *part, double tol2, double ref2, int max_it,
@@ -990,10 +1020,13 @@ static hipEvent_t take_event(Scene &s) {
   return s.ev_pool[s.ev_used++];
 }
 
-static void harvest_events(Scene &s) {
+// Adds the timed SpMV launches of one chunk that did work: pair c brackets
+// iteration first + c, and only iterations below n_real ran (later launches
+// of the chunk exit at once).
+static void harvest_events(Scene &s, int first, int n_real) {
   for (int k = 0; k + 1 < s.ev_used; k += 2) {
     float ms = 0.f;
-    if (hipEventElapsedTime(&ms, s.ev_pool[k], s.ev_pool[k + 1]) == hipSuccess) {
+    if (first + k / 2 < n_real && hipEventElapsedTime(&ms, s.ev_pool[k], s.ev_pool[k + 1]) == hipSuccess) {
       s.spmv_ms += ms;
       s.spmv_launches += 1;
     }
@@ -1006,8 +1039,7 @@ template <typename MT, typename VT, int NB>
 static int pcg_start(Scene &s, const double *rhs, double *xsol, bool start, double *part) {
   int N = s.N, n3 = 3 * N, nb = blocks_for(N, kBS);
   VT *p = static_cast<VT *>(s.pv.p), *q = static_cast<VT *>(s.q.p), *z = static_cast<VT *>(s.z.p);
-  const MT *val = static_cast<const MT *>(s.val.p), *D = static_cast<const MT *>(s.Dblk.p);
-  const MT *Dinv = static_cast<const MT *>(s.Dinv.p), *pblk = static_cast<const MT *>(s.pair_blk.p);
+  const MT *Dinv = static_cast<const MT *>(s.Dinv.p);
   const int *grp = s.group.as<int>();
   bool use_q = false;
   if (!start) {
@@ -1017,9 +1049,8 @@ static int pcg_start(Scene &s, const double *rhs, double *xsol, bool start, doub
       hipLaunchKernelGGL(k_to_vt_f, dim3(blocks_for(n3, kBS)), dim3(kBS), 0, s.stream, xsol, (float *)p, n3);
     else
       hipLaunchKernelGGL(k_copy_d, dim3(blocks_for(n3, kBS)), dim3(kBS), 0, s.stream, xsol, (double *)p, n3);
-    hipLaunchKernelGGL((k_spmv<MT, VT>), dim3(blocks_for((long)N * kG, kBS)), dim3(kBS), 0, s.stream, N,
-                       s.row_ptr.as<int>(), s.col_idx.as<int>(), val, D, s.coff_ptr.as<int>(), s.coff_col.as<int>(),
-                       s.coff_src.as<int>(), pblk, grp, NB > 1 ? 1 : 0, p, q);
+    hipLaunchKernelGGL((k_spmv<MT, VT>), dim3(spmv_grid(N)), dim3(kBS), 0, s.stream, N, bsr_view<MT>(s), grp,
+                       NB > 1 ? 1 : 0, p, q);
     use_q = true;
   }
   hipLaunchKernelGGL((k_pcg_init<MT, VT, NB>), dim3(nb), dim3(kBS), 0, s.stream, N, s.freev.as<uint8_t>(), Dinv, grp,
@@ -1064,25 +1095,17 @@ static bool capture_graph(Scene &s, hipGraphExec_t &exec, F launches) {
   return true;
 }
 
-static void ensure_graph_events(Scene &s, int n) {
-  while ((int)s.graph_ev.size() < n) {
-    hipEvent_t e;
-    hipEventCreate(&e);
-    s.graph_ev.push_back(e);
-  }
-}
-
 template <typename MT, typename VT>
 static int cg_run(Scene &s, const double *rhs, double *xsol, double tol, double ref2, int max_iters, bool start,
                   bool resume, int *iters_out, double *rnorm_out) {
-  int N = s.N, nb = blocks_for(N, kBS), nbs = blocks_for((long)N * kG, kBS);
+  int N = s.N, nb = blocks_for(N, kBS), nbs = spmv_grid(N);
   if (s.partial.grow((size_t)(nbs + 3 * nb) * sizeof(double)) || s.pcg_ctl.grow(sizeof(CgCtl))) return BAL_E_OOM;
   double *part_pq = s.partial.as<double>(), *part = part_pq + (size_t)nbs;
   CgCtl *ctl = s.pcg_ctl.as<CgCtl>();
   CgCtl *h = s.pin.as<CgCtl>();
   VT *p = static_cast<VT *>(s.pv.p), *q = static_cast<VT *>(s.q.p), *z = static_cast<VT *>(s.z.p);
-  const MT *val = static_cast<const MT *>(s.val.p), *D = static_cast<const MT *>(s.Dblk.p);
-  const MT *Dinv = static_cast<const MT *>(s.Dinv.p), *pblk = static_cast<const MT *>(s.pair_blk.p);
+  const BsrView<MT> B = bsr_view<MT>(s);
+  const MT *Dinv = static_cast<const MT *>(s.Dinv.p);
   double *r = s.r.as<double>();
   int k;
   if (resume) {
@@ -1108,33 +1131,36 @@ static int cg_run(Scene &s, const double *rhs, double *xsol, double tol, double 
   }
   const int chunk = 16;
   auto launch_iter = [&](int kk, hipEvent_t e0, hipEvent_t e1) {
-    if (e0) hipEventRecord(e0, s.stream);
-    hipLaunchKernelGGL((k_cg_spmv<MT, VT>), dim3(nbs), dim3(kBS), 0, s.stream, N, kk, s.row_ptr.as<int>(),
-                       s.col_idx.as<int>(), val, D, s.coff_ptr.as<int>(), s.coff_col.as<int>(), s.coff_src.as<int>(),
-                       pblk, p, q, ctl, part_pq);
-    if (e1) hipEventRecord(e1, s.stream);
+    // timed launches carry their own start/stop events (kernel execution only)
+    if (e0)
+      hipExtLaunchKernelGGL((k_cg_spmv<MT, VT>), dim3(nbs), dim3(kBS), 0, s.stream, e0, e1, 0, N, kk, B, p, q, ctl,
+                            part_pq);
+    else
+      hipLaunchKernelGGL((k_cg_spmv<MT, VT>), dim3(nbs), dim3(kBS), 0, s.stream, N, kk, B, p, q, ctl, part_pq);
     hipLaunchKernelGGL((k_cg_update<MT, VT>), dim3(nb), dim3(kBS), 0, s.stream, N, kk, s.freev.as<uint8_t>(), Dinv, p,
                        q, xsol, r, z, ctl, part_pq, nbs, part);
     hipLaunchKernelGGL((k_cg_dir<VT>), dim3(nb), dim3(kBS), 0, s.stream, N, kk, z, p, ctl, part_pq, nbs, part);
   };
-  // the kernels use only k & 1, so one capture serves every chunk that starts at an even k
-  std::vector<uintptr_t> sig = {(uintptr_t)s.row_ptr.p, (uintptr_t)s.col_idx.p, (uintptr_t)val, (uintptr_t)D,
-                                (uintptr_t)s.coff_ptr.p, (uintptr_t)s.coff_col.p, (uintptr_t)s.coff_src.p,
-                                (uintptr_t)pblk, (uintptr_t)p, (uintptr_t)q, (uintptr_t)ctl, (uintptr_t)part_pq,
-                                (uintptr_t)s.freev.p, (uintptr_t)Dinv, (uintptr_t)xsol, (uintptr_t)r, (uintptr_t)z,
-                                (uintptr_t)N, (uintptr_t)s.time_kernels};
+  // the kernels use only k & 1, so one capture serves every chunk that starts
+  // at an even k.  Kernel timing brackets every SpMV with events, which a
+  // captured graph does not time: timed solves launch eagerly.
+  std::vector<uintptr_t> sig = bsr_sig(B);
+  sig.insert(sig.end(), {(uintptr_t)p, (uintptr_t)q, (uintptr_t)ctl, (uintptr_t)part_pq, (uintptr_t)s.freev.p,
+                         (uintptr_t)Dinv, (uintptr_t)xsol, (uintptr_t)r, (uintptr_t)z, (uintptr_t)N});
   for (;;) {
     bool graphed = false;
-    if (s.use_graphs && (k & 1) == 0) {
+    const int first = k;
+    if (s.use_graphs && !s.time_kernels && (k & 1) == 0) {
       if (!graph_current(s.cg_sig, sig, s.cg_exec)) {
-        if (s.time_kernels) ensure_graph_events(s, 2 * chunk);
         bool ok = capture_graph(s, s.cg_exec, [&]() {
-          for (int c = 0; c < chunk; ++c)
-            launch_iter(c, s.time_kernels ? s.graph_ev[2 * c] : nullptr, s.time_kernels ? s.graph_ev[2 * c + 1] : nullptr);
+          for (int c = 0; c < chunk; ++c) launch_iter(c, nullptr, nullptr);
         });
         if (ok) s.cg_sig = sig; else { s.use_graphs = false; s.cg_sig.clear(); }
       }
-      if (s.use_graphs && hipGraphLaunch(s.cg_exec, s.stream) == hipSuccess) graphed = true;
+      if (s.use_graphs && hipGraphLaunch(s.cg_exec, s.stream) == hipSuccess) {
+        graphed = true;
+        ++s.graph_launches;
+      }
     }
     if (graphed) {
       k += chunk;
@@ -1147,23 +1173,9 @@ static int cg_run(Scene &s, const double *rhs, double *xsol, double tol, double 
     }
     hipMemcpyAsync(h, ctl, sizeof(CgCtl), hipMemcpyDeviceToHost, s.stream);
     if (hipStreamSynchronize(s.stream) != hipSuccess) return BAL_E_HIP;
-    if (s.time_kernels) {
-      if (graphed) {
-        for (int c = 0; c < chunk; ++c) {
-          float ms = 0.f;
-          if (hipEventElapsedTime(&ms, s.graph_ev[2 * c], s.graph_ev[2 * c + 1]) == hipSuccess) {
-            s.spmv_ms += ms;
-            s.spmv_launches += 1;
-          }
-        }
-      } else {
-        harvest_events(s);
-      }
-    }
     const CgSlot &sl = h->slot[h->slot[0].it >= h->slot[1].it ? 0 : 1];
+    if (s.time_kernels) harvest_events(s, first, sl.it);
     if (sl.done) {
-      // SpMV launches after the stop exit at once; do not count them as timed work
-      if (s.time_kernels) s.spmv_launches -= std::max(0, k - sl.it);
       *iters_out = sl.it;
       *rnorm_out = sl.rnorm;
       return sl.done == PCG_BREAKDOWN ? BAL_E_NO_CONVERGENCE : BAL_OK;
@@ -1173,13 +1185,13 @@ static int cg_run(Scene &s, const double *rhs, double *xsol, double tol, double 
 
 template <typename MT, typename VT>
 static int warm_run(Scene &s, const double *rhs, double *xsol, double tol, int max_iters, int *iters_out) {
-  int N = s.N, nb = blocks_for(N, kBS), nbs = blocks_for((long)N * kG, kBS);
+  int N = s.N, nb = blocks_for(N, kBS), nbs = spmv_grid(N);
   if (s.partial.grow((size_t)nbs * 3 * kGroups * sizeof(double)) || s.warm_ctl.grow(sizeof(WarmCtl))) return BAL_E_OOM;
   double *part = s.partial.as<double>();
   WarmCtl *ctl = s.warm_ctl.as<WarmCtl>();
   VT *p = static_cast<VT *>(s.pv.p), *q = static_cast<VT *>(s.q.p), *z = static_cast<VT *>(s.z.p);
-  const MT *val = static_cast<const MT *>(s.val.p), *D = static_cast<const MT *>(s.Dblk.p);
-  const MT *Dinv = static_cast<const MT *>(s.Dinv.p), *pblk = static_cast<const MT *>(s.pair_blk.p);
+  const BsrView<MT> B = bsr_view<MT>(s);
+  const MT *Dinv = static_cast<const MT *>(s.Dinv.p);
   const int *grp = s.group.as<int>();
   double *r = s.r.as<double>();
   pcg_start<MT, VT, kGroups>(s, rhs, xsol, false, part);
@@ -1187,20 +1199,17 @@ static int warm_run(Scene &s, const double *rhs, double *xsol, double tol, int m
   WarmCtl *h = s.pin.as<WarmCtl>();
   const int chunk = 8;
   auto launch_iter = [&]() {
-    hipLaunchKernelGGL((k_w_spmv<MT, VT>), dim3(nbs), dim3(kBS), 0, s.stream, N, s.row_ptr.as<int>(),
-                       s.col_idx.as<int>(), val, D, s.coff_ptr.as<int>(), s.coff_col.as<int>(), s.coff_src.as<int>(),
-                       pblk, grp, p, q, ctl, part);
+    hipLaunchKernelGGL((k_w_spmv<MT, VT>), dim3(nbs), dim3(kBS), 0, s.stream, N, B, grp, p, q, ctl, part);
     hipLaunchKernelGGL(k_w_alpha, dim3(1), dim3(kBS), 0, s.stream, nbs, ctl, part);
     hipLaunchKernelGGL((k_w_update<MT, VT>), dim3(nb), dim3(kBS), 0, s.stream, N, s.freev.as<uint8_t>(), Dinv, grp, p,
                        q, xsol, r, z, ctl, part);
     hipLaunchKernelGGL(k_w_beta, dim3(1), dim3(kBS), 0, s.stream, nb, ctl, part);
     hipLaunchKernelGGL((k_w_dir<VT>), dim3(nb), dim3(kBS), 0, s.stream, N, grp, z, p, ctl);
   };
-  std::vector<uintptr_t> sig = {(uintptr_t)s.row_ptr.p, (uintptr_t)s.col_idx.p, (uintptr_t)val, (uintptr_t)D,
-                                (uintptr_t)s.coff_ptr.p, (uintptr_t)s.coff_col.p, (uintptr_t)s.coff_src.p,
-                                (uintptr_t)pblk, (uintptr_t)grp, (uintptr_t)p, (uintptr_t)q, (uintptr_t)ctl,
-                                (uintptr_t)part, (uintptr_t)s.freev.p, (uintptr_t)Dinv, (uintptr_t)xsol, (uintptr_t)r,
-                                (uintptr_t)z, (uintptr_t)N};
+  std::vector<uintptr_t> sig = bsr_sig(B);
+  sig.insert(sig.end(), {(uintptr_t)grp, (uintptr_t)p, (uintptr_t)q, (uintptr_t)ctl, (uintptr_t)part,
+                         (uintptr_t)s.freev.p, (uintptr_t)Dinv, (uintptr_t)xsol, (uintptr_t)r, (uintptr_t)z,
+                         (uintptr_t)N});
   for (;;) {
     bool graphed = false;
     if (s.use_graphs) {
@@ -1210,7 +1219,10 @@ static int warm_run(Scene &s, const double *rhs, double *xsol, double tol, int m
         });
         if (ok) s.warm_sig = sig; else { s.use_graphs = false; s.warm_sig.clear(); }
       }
-      if (s.use_graphs && hipGraphLaunch(s.warm_exec, s.stream) == hipSuccess) graphed = true;
+      if (s.use_graphs && hipGraphLaunch(s.warm_exec, s.stream) == hipSuccess) {
+        graphed = true;
+        ++s.graph_launches;
+      }
     }
     if (!graphed)
       for (int c = 0; c < chunk; ++c) launch_iter();

@@ -203,6 +203,179 @@ def beam(nx=128, ny=16, nz=16, cell=0.01, seed=0, sigma_logE=0.3, meanE=1e6, nu=
                  dt=1.0 / 60.0, dhat=1e-3, n_steps=n_steps, v0=v0)
 
 
+def icosphere(level: int):
+    """Unit icosphere: the icosahedron with every triangle split into 4,
+    `level` times, new vertices pushed to the sphere.  Returns (verts (n,3),
+    faces (f,3) int64) with faces counter-clockwise seen from outside;
+    n = 10 * 4^level + 2, f = 20 * 4^level."""
+    t = (1.0 + 5.0 ** 0.5) / 2.0
+    v = [(-1, t, 0), (1, t, 0), (-1, -t, 0), (1, -t, 0), (0, -1, t), (0, 1, t), (0, -1, -t), (0, 1, -t),
+         (t, 0, -1), (t, 0, 1), (-t, 0, -1), (-t, 0, 1)]
+    f = [(0, 11, 5), (0, 5, 1), (0, 1, 7), (0, 7, 10), (0, 10, 11), (1, 5, 9), (5, 11, 4), (11, 10, 2),
+         (10, 7, 6), (7, 1, 8), (3, 9, 4), (3, 4, 2), (3, 2, 6), (3, 6, 8), (3, 8, 9), (4, 9, 5), (2, 4, 11),
+         (6, 2, 10), (8, 6, 7), (9, 8, 1)]
+    verts = [np.asarray(p, dtype=np.float64) / np.linalg.norm(p) for p in v]
+    faces = list(f)
+    for _ in range(level):
+        mid = {}
+
+        def midpoint(a, b):
+            key = (a, b) if a < b else (b, a)
+            if key not in mid:
+                m = verts[a] + verts[b]
+                verts.append(m / np.linalg.norm(m))
+                mid[key] = len(verts) - 1
+            return mid[key]
+
+        nxt = []
+        for a, b, c in faces:
+            ab, bc, ca = midpoint(a, b), midpoint(b, c), midpoint(c, a)
+            nxt += [(a, ab, ca), (b, bc, ab), (c, ca, bc), (ab, bc, ca)]
+        faces = nxt
+    return np.array(verts), np.array(faces, dtype=np.int64)
+
+
+# Prism symmetries taking vertex k to position 0 (bottom v0 v1 v2, top v3 v4 v5,
+# v_{i+3} above v_i), used by the prism split below.
+_PRISM_ROT = [(0, 1, 2, 3, 4, 5), (1, 2, 0, 4, 5, 3), (2, 0, 1, 5, 3, 4),
+              (3, 5, 4, 0, 2, 1), (4, 3, 5, 1, 0, 2), (5, 4, 3, 2, 1, 0)]
+
+
+def prism_to_tets(prisms):
+    """Split prisms (P,6) into 3 tets each so that neighbouring prisms agree.
+
+    Every quadrilateral face is cut by the diagonal through its vertex of
+    smallest global index (Dompierre et al., 1999): the prism is turned so
+    that its smallest vertex is v0, which fixes the two quads through v0, and
+    the third quad (v1 v2 v5 v4) is cut through min(v1, v5) vs min(v2, v4).
+    """
+    prisms = np.asarray(prisms, dtype=np.int64)
+    rot = np.array(_PRISM_ROT)[np.argmin(prisms, axis=1)]
+    v = np.take_along_axis(prisms, rot, axis=1)
+    v0, v1, v2, v3, v4, v5 = v.T
+    a = np.minimum(v1, v5) < np.minimum(v2, v4)
+    t1 = np.where(a[:, None], np.stack([v0, v1, v2, v5], 1), np.stack([v0, v1, v2, v4], 1))
+    t2 = np.where(a[:, None], np.stack([v0, v1, v5, v4], 1), np.stack([v0, v4, v2, v5], 1))
+    t3 = np.stack([v0, v4, v5, v3], 1)
+    return np.stack([t1, t2, t3], 1).reshape(-1, 4)
+
+
+def hollow_sphere(level: int, layers: int, r_in: float, r_out: float, centre=(0.0, 0.0, 0.0)):
+    """Spherical shell: icosphere `level` surface, `layers` radial layers of
+    prisms between r_in and r_out, 3 tets per prism.  Vertex (l, v) of layer
+    l = 0..layers has index l * n_surface + v."""
+    sv, sf = icosphere(level)
+    nv = sv.shape[0]
+    radii = np.linspace(r_in, r_out, layers + 1)
+    pos = np.concatenate([sv * r for r in radii]) + np.asarray(centre, dtype=np.float64)
+    prisms = np.concatenate([np.concatenate([sf + l * nv, sf + (l + 1) * nv], axis=1) for l in range(layers)])
+    tets = orient_positive(pos, prism_to_tets(prisms))
+    return pos, tets.astype(np.int32)
+
+
+# Kuhn split of a cube into 6 tets along the diagonal 000 -> 111: one tet per
+# order in which the three axes are stepped.
+_KUHN = [(0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)]
+
+
+def tube_ring(centre, e1, e2, e3, R: float, half: float, n_u: int):
+    """Closed square-section tube (a torus link) of centre-line radius R in
+    the plane (e1, e2) through `centre`; the section is the square
+    [-half, half]^2 in the (radial, e3) directions, split 2 x 2.  Each of the
+    n_u x 2 x 2 hexahedral cells is cut into 6 tets (Kuhn split, conforming
+    across cells and across the seam).  Vertex (u, a, b) has index
+    (u * 3 + a) * 3 + b."""
+    centre, e1, e2, e3 = (np.asarray(x, dtype=np.float64) for x in (centre, e1, e2, e3))
+    u = np.arange(n_u)[:, None, None]
+    a = np.arange(3)[None, :, None]
+    b = np.arange(3)[None, None, :]
+    th = 2.0 * np.pi * u / n_u
+    rad = R + (a - 1) * half
+    off = (b - 1) * half
+    pos = (centre + (rad * np.cos(th))[..., None] * e1 + (rad * np.sin(th))[..., None] * e2
+           + (off + 0.0 * th)[..., None] * e3).reshape(-1, 3)
+
+    def vid(uu, aa, bb):
+        return ((uu % n_u) * 3 + aa) * 3 + bb
+
+    cu, ca, cb = (x.ravel() for x in np.meshgrid(np.arange(n_u), np.arange(2), np.arange(2), indexing="ij"))
+    tets = []
+    for order in _KUHN:
+        step = np.zeros(3, dtype=np.int64)
+        corners = [vid(cu, ca, cb)]
+        for axis in order:
+            step[axis] += 1
+            corners.append(vid(cu + step[0], ca + step[1], cb + step[2]))
+        tets.append(np.stack(corners, 1))
+    tets = np.stack(tets, 1).reshape(-1, 4)
+    return pos, orient_positive(pos, tets).astype(np.int32)
+
+
+def chain_net(sites=40, pitch=0.025, R_flat=0.02, R_link=0.015, half=0.003, n_u=10,
+              sphere_level=4, sphere_layers=2, r_in=0.08, r_out=0.1, n_steps=5,
+              E_net=1e9, nu_net=0.3, E_sphere=5e5, nu_sphere=0.4):
+    """Four hollow spheres falling onto a chain net of tet-meshed torus links.
+
+    Net: a sites x sites grid of pitch `pitch` in the xz-plane (y = 0).  Flat
+    rings (axis y, centre-line radius R_flat) sit at the (even, even) sites;
+    connector rings (radius R_link) sit at the (odd, even) sites in the
+    xy-plane and at the (even, odd) sites in the yz-plane, each threading its
+    two flat neighbours.  With pitch 2.5 cm, R_flat 2 cm, R_link 1.5 cm and a
+    6 mm square section the flat rings stay 5 mm apart and every threaded
+    pair keeps at least 1 mm of clearance (the link crossings lie at the
+    middle of the links' straight segments).  The flat rings on the border of
+    the net are fixed.  Spheres: shells r_in..r_out, at (+-0.2, ., +-0.2),
+    5 mm above the net's top.  The default (40 x 40 sites, 1160 links of
+    n_u = 10, spheres of level 4 x 2 layers) has 401,280 tets.
+    """
+    ex, ey, ez = np.eye(3)
+    pos_all, tets_all, E_all, nu_all, fixed_all = [], [], [], [], []
+    nbase = 0
+
+    def add(pos, tets, E, nu, fixed):
+        nonlocal nbase
+        pos_all.append(pos)
+        tets_all.append(tets.astype(np.int64) + nbase)
+        E_all.append(np.full(tets.shape[0], E))
+        nu_all.append(np.full(tets.shape[0], nu))
+        fixed_all.append(np.full(pos.shape[0], 1 if fixed else 0, np.uint8))
+        nbase += pos.shape[0]
+
+    c0 = -0.5 * (sites - 1) * pitch
+    for i in range(sites):
+        for k in range(sites):
+            centre = np.array([c0 + i * pitch, 0.0, c0 + k * pitch])
+            if i % 2 == 0 and k % 2 == 0:
+                border = i == 0 or k == 0 or i == sites - 2 + (sites % 2) or k == sites - 2 + (sites % 2)
+                p, t = tube_ring(centre, ex, ez, ey, R_flat, half, n_u)
+                add(p, t, E_net, nu_net, border)
+            elif i % 2 == 1 and k % 2 == 0 and i + 1 < sites:
+                p, t = tube_ring(centre, ex, ey, ez, R_link, half, n_u)
+                add(p, t, E_net, nu_net, False)
+            elif i % 2 == 0 and k % 2 == 1 and k + 1 < sites:
+                p, t = tube_ring(centre, ez, ey, ex, R_link, half, n_u)
+                add(p, t, E_net, nu_net, False)
+    top = R_link + half
+    for sx in (-0.2, 0.2):
+        for sz in (-0.2, 0.2):
+            p, t = hollow_sphere(sphere_level, sphere_layers, r_in, r_out, (sx, top + 0.005 + r_out, sz))
+            add(p, t, E_sphere, nu_sphere, False)
+    pos = np.concatenate(pos_all)
+    tets = np.concatenate(tets_all)
+    name = f"chain_net_{sites}x{sites}_nu{n_u}_L{sphere_level}x{sphere_layers}"
+    sc = _pack(name, pos, tets, 1.0, 0.3, 1000.0, np.concatenate(fixed_all), np.zeros((0, 3)),
+               np.zeros((0, 3), np.int32), dt=1.0 / 30.0, dhat=1e-3, n_steps=n_steps)
+    sc["youngs"] = np.concatenate(E_all)
+    sc["poisson"] = np.concatenate(nu_all)
+    return sc
+
+
+def chain_net_large(E_net=1e9):
+    """The chain-net scene refined: spheres of level 5 x 4 layers and links of
+    n_u = 28 (1,762,560 tets), one step."""
+    return chain_net(n_u=28, sphere_level=5, sphere_layers=4, n_steps=1, E_net=E_net)
+
+
 def spmv_grid(n=128, cell=0.01, seed=2, amplitude=0.1):
     """Large regular grid for the block-SpMV roofline (no contact).
 
