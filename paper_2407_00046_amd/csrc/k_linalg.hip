@@ -552,28 +552,38 @@ __device__ __forceinline__ void blk_mtv(const MT *__restrict__ a, const VT *__re
   acc[2] += (VT)a[2] * w0 + (VT)a[5] * w1 + (VT)a[8] * w2;
 }
 
-template <typename MT, typename VT>
-__device__ __forceinline__ void spmv_row(int i, int g, const BsrView<MT> &B, const int *__restrict__ grp, int masked,
+template <typename MT, typename VT, bool MASK>
+__device__ __forceinline__ void spmv_row(int i, int g, const BsrView<MT> &B, const int *__restrict__ grp,
                                          const VT *__restrict__ v, VT *acc) {
   acc[0] = acc[1] = acc[2] = (VT)0;
   if (i >= 0) {
-    int gi = masked ? grp[i] : 0;
-    const int l0 = B.rp[i], nl = B.rp[i + 1] - l0, u0 = B.up[i], nt = nl + (B.up[i + 1] - u0);
-    for (int t = g; t < nt; t += kG) {
-      if (t < nl) {
-        int k = l0 + t, j = B.ci[k];
-        if (masked && grp[j] != gi) continue;
-        blk_mv<MT, VT>(B.val + (size_t)9 * k, v, j, acc);
-      } else {
-        int2 e = B.ue[u0 + t - nl];
-        if (masked && grp[e.x] != gi) continue;
-        blk_mtv<MT, VT>(B.val + (size_t)9 * e.y, v, e.x, acc);
-      }
+    const int gi = MASK ? grp[i] : 0;
+    const int l0 = B.rp[i], l1 = B.rp[i + 1], u0 = B.up[i], u1 = B.up[i + 1];
+    // the row's own blocks, two per pass so that both gathers are in flight together
+    int k = l0 + g;
+    for (; k + kG < l1; k += 2 * kG) {
+      const int j0 = B.ci[k], j1 = B.ci[k + kG];
+      if (!MASK || grp[j0] == gi) blk_mv<MT, VT>(B.val + (size_t)9 * k, v, j0, acc);
+      if (!MASK || grp[j1] == gi) blk_mv<MT, VT>(B.val + (size_t)9 * (k + kG), v, j1, acc);
     }
-    for (int k = B.cp[i] + g; k < B.cp[i + 1]; k += kG) {
-      int j = B.cc[k];
-      if (masked && grp[j] != gi) continue;
-      blk_mv<MT, VT>(B.pblk + (size_t)9 * B.cs[k], v, j, acc);
+    if (k < l1) {
+      const int j = B.ci[k];
+      if (!MASK || grp[j] == gi) blk_mv<MT, VT>(B.val + (size_t)9 * k, v, j, acc);
+    }
+    // the blocks of column i, stored in the rows below, applied transposed
+    int e = u0 + g;
+    for (; e + kG < u1; e += 2 * kG) {
+      const int2 x0 = B.ue[e], x1 = B.ue[e + kG];
+      if (!MASK || grp[x0.x] == gi) blk_mtv<MT, VT>(B.val + (size_t)9 * x0.y, v, x0.x, acc);
+      if (!MASK || grp[x1.x] == gi) blk_mtv<MT, VT>(B.val + (size_t)9 * x1.y, v, x1.x, acc);
+    }
+    if (e < u1) {
+      const int2 x = B.ue[e];
+      if (!MASK || grp[x.x] == gi) blk_mtv<MT, VT>(B.val + (size_t)9 * x.y, v, x.x, acc);
+    }
+    for (int c = B.cp[i] + g; c < B.cp[i + 1]; c += kG) {
+      const int j = B.cc[c];
+      if (!MASK || grp[j] == gi) blk_mv<MT, VT>(B.pblk + (size_t)9 * B.cs[c], v, j, acc);
     }
   }
 #pragma unroll
@@ -583,13 +593,13 @@ __device__ __forceinline__ void spmv_row(int i, int g, const BsrView<MT> &B, con
   if (i >= 0 && g == 0) blk_mv<MT, VT>(B.D + (size_t)9 * i, v, i, acc);
 }
 
-template <typename MT, typename VT>
-__global__ __launch_bounds__(kBS) void k_spmv(int N, BsrView<MT> B, const int *__restrict__ grp, int masked,
+template <typename MT, typename VT, bool MASK>
+__global__ __launch_bounds__(kBS) void k_spmv(int N, BsrView<MT> B, const int *__restrict__ grp,
                                               const VT *__restrict__ v, VT *__restrict__ out) {
   long t = (long)xcd_tile() * blockDim.x + threadIdx.x;
   int i = (int)(t / kG), g = (int)(t % kG);
   VT acc[3];
-  spmv_row<MT, VT>(i < N ? i : -1, g, B, grp, masked, v, acc);
+  spmv_row<MT, VT, MASK>(i < N ? i : -1, g, B, grp, v, acc);
   if (i < N && g == 0) {
     out[3 * i] = acc[0];
     out[3 * i + 1] = acc[1];
@@ -597,14 +607,22 @@ __global__ __launch_bounds__(kBS) void k_spmv(int N, BsrView<MT> B, const int *_
   }
 }
 
-void launch_spmv(Scene &s, const void *vin, void *vout, int masked) {
+template <typename MT, typename VT>
+static void launch_spmv_t(Scene &s, const void *vin, void *vout, int masked) {
   dim3 g(spmv_grid(s.N)), b(kBS);
-  if (s.mixed)
-    hipLaunchKernelGGL((k_spmv<float, float>), g, b, 0, s.stream, s.N, bsr_view<float>(s), s.group.as<int>(), masked,
-                       static_cast<const float *>(vin), static_cast<float *>(vout));
+  if (masked)
+    hipLaunchKernelGGL((k_spmv<MT, VT, true>), g, b, 0, s.stream, s.N, bsr_view<MT>(s), s.group.as<int>(),
+                       static_cast<const VT *>(vin), static_cast<VT *>(vout));
   else
-    hipLaunchKernelGGL((k_spmv<double, double>), g, b, 0, s.stream, s.N, bsr_view<double>(s), s.group.as<int>(),
-                       masked, static_cast<const double *>(vin), static_cast<double *>(vout));
+    hipLaunchKernelGGL((k_spmv<MT, VT, false>), g, b, 0, s.stream, s.N, bsr_view<MT>(s), s.group.as<int>(),
+                       static_cast<const VT *>(vin), static_cast<VT *>(vout));
+}
+
+void launch_spmv(Scene &s, const void *vin, void *vout, int masked) {
+  if (s.mixed)
+    launch_spmv_t<float, float>(s, vin, vout, masked);
+  else
+    launch_spmv_t<double, double>(s, vin, vout, masked);
 }
 
 double spmv_bytes(const Scene &s) {
@@ -658,7 +676,8 @@ __device__ __forceinline__ void wave_bin_sums(int bin, double v, double *wave_ou
   }
 }
 
-// Block per-bin sums written to part[(v * nbk + blk) * NB + bin], nbk = gridDim.x.
+// Block per-bin sums written bin-major, part[(v * NB + bin) * nbk + blk] with
+// nbk = gridDim.x, so that one bin's partials are contiguous.
 template <int NB, int NV>
 __device__ void block_partials(int bin, const double *vals, double *part, int blk) {
   constexpr int W = kBS / 64;
@@ -685,12 +704,11 @@ __device__ void block_partials(int bin, const double *vals, double *part, int bl
     double acc = 0.0;
 #pragma unroll
     for (int q = 0; q < W; ++q) acc += (&wsum[q][0][0])[k];
-    int v = k / NB, b = k % NB;
-    part[((size_t)v * nbk + blk) * NB + b] = acc;
+    part[(size_t)k * nbk + blk] = acc;
   }
 }
 
-// tot[v][b] = sum over nbk blocks of part[(v * nbk + block) * NB + b]; one
+// tot[v][b] = sum over nbk blocks of part[(v * NB + b) * nbk + block]; one
 // wave per entry, lanes striding over blocks, fixed shuffle tree.  All
 // threads of the calling block see the result (after the barrier).
 template <int NB, int NV>
@@ -699,7 +717,7 @@ __device__ void sum_blocks(const double *part, int nbk, double (*tot)[NB]) {
   for (int k = w; k < NV * NB; k += nw) {
     int v = k / NB, b = k % NB;
     double acc = 0.0;
-    for (int j = lane; j < nbk; j += 64) acc += part[((size_t)v * nbk + j) * NB + b];
+    for (int j = lane; j < nbk; j += 64) acc += part[(size_t)k * nbk + j];
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
     if (lane == 0) tot[v][b] = acc;
@@ -735,7 +753,7 @@ __device__ __forceinline__ void spmv_partial(int N, const BsrView<MT> &B, const 
   int bin = -1;
   int i = (int)(t / kG), g = (int)(t % kG);
   VT acc[3];
-  spmv_row<MT, VT>(i < N ? i : -1, g, B, grp, NB > 1, p, acc);
+  spmv_row<MT, VT, (NB > 1)>(i < N ? i : -1, g, B, grp, p, acc);
   if (i < N && g == 0) {
     q[3 * i] = acc[0];
     q[3 * i + 1] = acc[1];
@@ -854,15 +872,26 @@ __global__ __launch_bounds__(kBS) void k_w_spmv(int N, BsrView<MT> B, const int 
   spmv_partial<MT, VT, kGroups>(N, B, grp, p, q, part);
 }
 
+// One block per group bin: the sum of that bin's partials (bin-major
+// layout, contiguous), reduced in a fixed order and seen by every thread.
+__device__ double bin_sum(const double *part, int nbk, int k) {
+  double acc = 0.0;
+  for (int j = threadIdx.x; j < nbk; j += blockDim.x) acc += part[(size_t)k * nbk + j];
+  return block_reduce(acc, OpSum(), 0.0);
+}
+
 __global__ void k_w_alpha(int nbk, WarmCtl *ctl, const double *part) {
+  const int b = blockIdx.x;
   if (ctl->done) return;
-  __shared__ double tot[1][kGroups];
-  sum_blocks<kGroups, 1>(part, nbk, tot);
-  for (int b = threadIdx.x; b < kGroups; b += blockDim.x) {
-    double pq = tot[0][b];
-    bool ok = ctl->active[b] && pq > 0.0;
+  if (!ctl->active[b]) {
+    if (threadIdx.x == 0) ctl->alpha[b] = 0.0;
+    return;
+  }
+  double pq = bin_sum(part, nbk, b);
+  if (threadIdx.x == 0) {
+    bool ok = pq > 0.0;
     ctl->alpha[b] = ok ? ctl->rz[b] / pq : 0.0;
-    if (ctl->active[b] && !(pq > 0.0)) ctl->active[b] = 0;
+    if (!ok) ctl->active[b] = 0;
   }
 }
 
@@ -878,29 +907,40 @@ __global__ __launch_bounds__(kBS) void k_w_update(int N, const uint8_t *__restri
 }
 
 __global__ void k_w_beta(int nbk, WarmCtl *ctl, const double *part) {
+  const int b = blockIdx.x;
   if (ctl->done) return;
-  __shared__ double tot[2][kGroups];
-  sum_blocks<kGroups, 2>(part, nbk, tot);
-  __shared__ int any;
-  if (threadIdx.x == 0) any = 0;
-  __syncthreads();
-  for (int b = threadIdx.x; b < kGroups; b += blockDim.x) {
-    if (!ctl->active[b]) { ctl->beta[b] = 0.0; continue; }
-    ctl->beta[b] = ctl->rz[b] != 0.0 ? tot[0][b] / ctl->rz[b] : 0.0;
-    ctl->rz[b] = tot[0][b];
-    ctl->rr[b] = tot[1][b];
-    if (tot[1][b] <= ctl->tol2 * ctl->ref2[b]) ctl->active[b] = 0;
-    if (ctl->active[b]) atomicOr(&any, 1);
+  if (!ctl->active[b]) {
+    if (threadIdx.x == 0) ctl->beta[b] = 0.0;
+    return;
   }
-  __syncthreads();
+  double rz = bin_sum(part, nbk, b), rr = bin_sum(part, nbk, kGroups + b);
   if (threadIdx.x == 0) {
-    double rr = 0.0;
-    for (int b = 0; b < kGroups; ++b) rr += tot[1][b];
-    ctl->rnorm = sqrt(rr);
-    ctl->it += 1;
-    if (!any) ctl->done = PCG_CONVERGED;
-    else if (ctl->it >= ctl->max_it) ctl->done = PCG_CAPPED;
+    ctl->beta[b] = ctl->rz[b] != 0.0 ? rz / ctl->rz[b] : 0.0;
+    ctl->rz[b] = rz;
+    ctl->rr[b] = rr;
+    if (rr <= ctl->tol2 * ctl->ref2[b]) ctl->active[b] = 0;
   }
+}
+
+// After the per-bin updates: iteration count, total residual and the stop
+// decision (one thread); kept apart so that every block of the direction
+// update below reads the same decision.
+__device__ void warm_bookkeeping(WarmCtl *ctl) {
+  double rr = 0.0;
+  int any = 0;
+  for (int b = 0; b < kGroups; ++b) {
+    rr += ctl->rr[b];
+    any |= ctl->active[b];
+  }
+  ctl->rnorm = sqrt(rr);
+  ctl->it += 1;
+  if (!any) ctl->done = PCG_CONVERGED;
+  else if (ctl->it >= ctl->max_it) ctl->done = PCG_CAPPED;
+}
+
+__global__ void k_w_check(WarmCtl *ctl) {
+  if (ctl->done || threadIdx.x != 0) return;
+  warm_bookkeeping(ctl);
 }
 
 template <typename VT>
@@ -978,28 +1018,32 @@ __global__ void k_cg_init_finish(int nbk, CgCtl *ctl, const double *part, double
   }
 }
 
-__global__ void k_w_init_finish(int nbk, WarmCtl *ctl, const double *part, double tol2, int max_it) {
-  __shared__ double tot[3][kGroups];
-  sum_blocks<kGroups, 3>(part, nbk, tot);
+__global__ void k_w_init_bins(int nbk, WarmCtl *ctl, const double *part, double tol2) {
+  const int b = blockIdx.x;
+  double rz = bin_sum(part, nbk, b), rr = bin_sum(part, nbk, kGroups + b), bb = bin_sum(part, nbk, 2 * kGroups + b);
   if (threadIdx.x == 0) {
-    double rr = 0.0;
-    int any = 0;
-    for (int b = 0; b < kGroups; ++b) {
-      ctl->rz[b] = tot[0][b];
-      ctl->rr[b] = tot[1][b];
-      ctl->ref2[b] = tot[2][b];
-      ctl->active[b] = tot[2][b] > 0.0 && tot[1][b] > tol2 * tot[2][b];
-      ctl->alpha[b] = 0.0;
-      ctl->beta[b] = 0.0;
-      rr += tot[1][b];
-      any |= ctl->active[b];
-    }
-    ctl->tol2 = tol2;
-    ctl->rnorm = sqrt(rr);
-    ctl->it = 0;
-    ctl->max_it = max_it;
-    ctl->done = any ? (max_it > 0 ? PCG_RUN : PCG_CAPPED) : PCG_CONVERGED;
+    ctl->rz[b] = rz;
+    ctl->rr[b] = rr;
+    ctl->ref2[b] = bb;
+    ctl->active[b] = bb > 0.0 && rr > tol2 * bb;
+    ctl->alpha[b] = 0.0;
+    ctl->beta[b] = 0.0;
   }
+}
+
+__global__ void k_w_init_done(WarmCtl *ctl, double tol2, int max_it) {
+  if (threadIdx.x != 0) return;
+  double rr = 0.0;
+  int any = 0;
+  for (int b = 0; b < kGroups; ++b) {
+    rr += ctl->rr[b];
+    any |= ctl->active[b];
+  }
+  ctl->tol2 = tol2;
+  ctl->rnorm = sqrt(rr);
+  ctl->it = 0;
+  ctl->max_it = max_it;
+  ctl->done = any ? (max_it > 0 ? PCG_RUN : PCG_CAPPED) : PCG_CONVERGED;
 }
 
 __global__ void k_to_vt_f(const double *__restrict__ a, float *__restrict__ b, int n) {
@@ -1049,8 +1093,7 @@ static int pcg_start(Scene &s, const double *rhs, double *xsol, bool start, doub
       hipLaunchKernelGGL(k_to_vt_f, dim3(blocks_for(n3, kBS)), dim3(kBS), 0, s.stream, xsol, (float *)p, n3);
     else
       hipLaunchKernelGGL(k_copy_d, dim3(blocks_for(n3, kBS)), dim3(kBS), 0, s.stream, xsol, (double *)p, n3);
-    hipLaunchKernelGGL((k_spmv<MT, VT>), dim3(spmv_grid(N)), dim3(kBS), 0, s.stream, N, bsr_view<MT>(s), grp,
-                       NB > 1 ? 1 : 0, p, q);
+    launch_spmv_t<MT, VT>(s, p, q, NB > 1 ? 1 : 0);
     use_q = true;
   }
   hipLaunchKernelGGL((k_pcg_init<MT, VT, NB>), dim3(nb), dim3(kBS), 0, s.stream, N, s.freev.as<uint8_t>(), Dinv, grp,
@@ -1195,15 +1238,17 @@ static int warm_run(Scene &s, const double *rhs, double *xsol, double tol, int m
   const int *grp = s.group.as<int>();
   double *r = s.r.as<double>();
   pcg_start<MT, VT, kGroups>(s, rhs, xsol, false, part);
-  hipLaunchKernelGGL(k_w_init_finish, dim3(1), dim3(kBS), 0, s.stream, nb, ctl, part, tol * tol, max_iters);
+  hipLaunchKernelGGL(k_w_init_bins, dim3(kGroups), dim3(kBS), 0, s.stream, nb, ctl, part, tol * tol);
+  hipLaunchKernelGGL(k_w_init_done, dim3(1), dim3(64), 0, s.stream, ctl, tol * tol, max_iters);
   WarmCtl *h = s.pin.as<WarmCtl>();
   const int chunk = 8;
   auto launch_iter = [&]() {
     hipLaunchKernelGGL((k_w_spmv<MT, VT>), dim3(nbs), dim3(kBS), 0, s.stream, N, B, grp, p, q, ctl, part);
-    hipLaunchKernelGGL(k_w_alpha, dim3(1), dim3(kBS), 0, s.stream, nbs, ctl, part);
+    hipLaunchKernelGGL(k_w_alpha, dim3(kGroups), dim3(kBS), 0, s.stream, nbs, ctl, part);
     hipLaunchKernelGGL((k_w_update<MT, VT>), dim3(nb), dim3(kBS), 0, s.stream, N, s.freev.as<uint8_t>(), Dinv, grp, p,
                        q, xsol, r, z, ctl, part);
-    hipLaunchKernelGGL(k_w_beta, dim3(1), dim3(kBS), 0, s.stream, nb, ctl, part);
+    hipLaunchKernelGGL(k_w_beta, dim3(kGroups), dim3(kBS), 0, s.stream, nb, ctl, part);
+    hipLaunchKernelGGL(k_w_check, dim3(1), dim3(64), 0, s.stream, ctl);
     hipLaunchKernelGGL((k_w_dir<VT>), dim3(nb), dim3(kBS), 0, s.stream, N, grp, z, p, ctl);
   };
   std::vector<uintptr_t> sig = bsr_sig(B);
