@@ -180,7 +180,7 @@ def main():
     roof = None
     if ach:
         roof = dict(bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS, traffic=None,
-                    kernel="k_cg_spmv<float,float>", bytes_per_launch=mixed["spmv_bytes"],
+                    kernel="k_cg_dir_spmv<float,float>", bytes_per_launch=mixed["spmv_bytes"],
                     avg_launch_ms=mixed["spmv_ms_avg"])
     line = dict(
         metric="s/timestep & PCG iters/s, mixed vs FP64 at 1e-4 tol; BSR SpMV HBM GB/s",

@@ -100,14 +100,15 @@ typedef struct bal_step_stats {
   int32_t n_aug_max;           /* max |A'| over the step */
   int32_t converged;           /* 1 if the Newton test passed */
   int32_t ls_retries;          /* line searches that fell below alpha 1e-9 and resumed PCG */
-  int32_t spmv_launches;       /* SpMV launches timed (when kernel timing is on) */
+  int32_t spmv_launches;       /* PCG product launches timed (when kernel timing is on) */
   int32_t graph_launches;      /* PCG chunks replayed as HIP graphs (0: launched one by one) */
   int32_t reserved;
   double sigma;                /* final penalty sigma (0 if never initialised) */
   double min_dist;             /* min pair distance at the end of the step (dhat if none closer) */
   double sec_total, sec_pcg, sec_hessian, sec_ccd, sec_collision, sec_linesearch;
-  double spmv_ms;              /* summed SpMV kernel time (hipEvents; kernel timing on) */
-  double spmv_bytes;           /* algorithmic bytes of one SpMV at the last matrix */
+  double spmv_ms;              /* summed PCG product kernel time (hipEvents; kernel timing on) */
+  double spmv_bytes;           /* algorithmic bytes of one PCG product launch at the last matrix:
+                                  the symmetric block SpMV plus reading z and writing the new direction */
 } bal_step_stats;
 
 /* Fills *d with defaults (all pointers NULL, sizes 0). */

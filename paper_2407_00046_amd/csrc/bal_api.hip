@@ -477,7 +477,7 @@ static int newton_solve(Scene &s, bal_step_stats *st, bool record) {
   S.spmv_ms = s.spmv_ms;
   S.spmv_launches = s.spmv_launches;
   S.graph_launches = s.graph_launches;
-  S.spmv_bytes = spmv_bytes(s);
+  S.spmv_bytes = cg_product_bytes(s);
   if ((rc = sync(s))) return rc;
   S.sec_total = since(t_start);
   s.last = S;
@@ -865,7 +865,7 @@ void bal_destroy_scene(bal_scene *h) {
                   &s.aug_d, &s.aug_e, &s.aug_tmp_mu, &s.aug_tmp_s, &s.hb_lo, &s.hb_hi, &s.hq_lo, &s.hq_hi,
                   &s.h_cnt, &s.h_off, &s.h_key, &s.h_prim, &s.h_bcnt, &s.h_bstart, &s.h_bfill, &s.h_skey,
                   &s.h_sprim, &s.h_large, &s.h_nlarge, &s.h_qcnt, &s.h_qoff, &s.h_out, &s.qoff_pt, &s.out_pt,
-                  &s.qoff_ee, &s.out_ee, &s.r, &s.z, &s.pv, &s.q, &s.pcg_ctl, &s.warm_ctl, &s.partial, &s.counter,
+                  &s.qoff_ee, &s.out_ee, &s.r, &s.z, &s.pv, &s.pv2, &s.q, &s.pcg_ctl, &s.warm_ctl, &s.partial, &s.counter,
                   &s.scan_tmp, &s.red_out, &s.flags, &s.node_e, &s.cand_e, &s.mask, &s.mask_off, &s.tau, &s.rhs};
   for (DBuf *b : bufs) b->release();
   PairList *pls[] = {&s.cand, &s.cand2, &s.uni, &s.augtmp};

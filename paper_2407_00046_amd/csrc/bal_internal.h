@@ -75,7 +75,7 @@ struct Scene {
   DBuf hb_lo, hb_hi, hq_lo, hq_hi, h_cnt, h_off, h_key, h_prim, h_bcnt, h_bstart, h_bfill, h_skey, h_sprim,
       h_large, h_nlarge, h_qcnt, h_qoff, h_out, qoff_pt, out_pt, qoff_ee, out_ee;
   // PCG
-  DBuf r, z, pv, q, pcg_ctl, warm_ctl, partial, counter, scan_tmp, red_out, flags;
+  DBuf r, z, pv, pv2, q, pcg_ctl, warm_ctl, partial, counter, scan_tmp, red_out, flags;
   DBuf node_e, cand_e, mask, mask_off, tau, rhs;
   DBuf pin;     // pinned host scratch (hipHostMalloc)
   // graph replay of PCG chunks (re-captured when a buffer moves)
@@ -127,6 +127,7 @@ int pcg_solve(Scene &s, const double *rhs, double *xsol, double rtol_ref, int ma
               int resume, int *iters_out, double *rel_out);
 int warm_start_solve(Scene &s, const double *rhs, double *xsol, double tol, int max_iters, int *iters_out);
 double spmv_bytes(const Scene &s);
+double cg_product_bytes(const Scene &s);
 double dot_free(Scene &s, const double *a, const double *b);
 
 // helpers

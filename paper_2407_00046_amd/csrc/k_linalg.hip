@@ -537,25 +537,49 @@ inline int spmv_grid(int N) {
   return (nb + 7) & ~7;
 }
 
+// Vector operand of the product: read as stored, or (the CG direction)
+// formed as p = z + beta p_old where it is read, in the same expression as
+// the row owner uses to store it, so every reader sees identical values.
+template <typename VT>
+struct VecPlain {
+  const VT *__restrict__ v;
+  __device__ __forceinline__ void load(int j, VT *w) const {
+    w[0] = v[3 * j];
+    w[1] = v[3 * j + 1];
+    w[2] = v[3 * j + 2];
+  }
+};
+template <typename VT>
+struct VecDir {
+  const VT *__restrict__ z;
+  const VT *__restrict__ p;
+  double beta;
+  __device__ __forceinline__ void load(int j, VT *w) const {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) w[c] = (VT)((double)z[3 * j + c] + beta * (double)p[3 * j + c]);
+  }
+};
+
 template <typename MT, typename VT>
-__device__ __forceinline__ void blk_mv(const MT *__restrict__ a, const VT *__restrict__ v, int j, VT *acc) {
-  VT w0 = v[3 * j], w1 = v[3 * j + 1], w2 = v[3 * j + 2];
-  acc[0] += (VT)a[0] * w0 + (VT)a[1] * w1 + (VT)a[2] * w2;
-  acc[1] += (VT)a[3] * w0 + (VT)a[4] * w1 + (VT)a[5] * w2;
-  acc[2] += (VT)a[6] * w0 + (VT)a[7] * w1 + (VT)a[8] * w2;
+__device__ __forceinline__ void blk_mv(const MT *__restrict__ a, const VT *w, VT *acc) {
+  acc[0] += (VT)a[0] * w[0] + (VT)a[1] * w[1] + (VT)a[2] * w[2];
+  acc[1] += (VT)a[3] * w[0] + (VT)a[4] * w[1] + (VT)a[5] * w[2];
+  acc[2] += (VT)a[6] * w[0] + (VT)a[7] * w[1] + (VT)a[8] * w[2];
 }
 template <typename MT, typename VT>
-__device__ __forceinline__ void blk_mtv(const MT *__restrict__ a, const VT *__restrict__ v, int j, VT *acc) {
-  VT w0 = v[3 * j], w1 = v[3 * j + 1], w2 = v[3 * j + 2];
-  acc[0] += (VT)a[0] * w0 + (VT)a[3] * w1 + (VT)a[6] * w2;
-  acc[1] += (VT)a[1] * w0 + (VT)a[4] * w1 + (VT)a[7] * w2;
-  acc[2] += (VT)a[2] * w0 + (VT)a[5] * w1 + (VT)a[8] * w2;
+__device__ __forceinline__ void blk_mtv(const MT *__restrict__ a, const VT *w, VT *acc) {
+  acc[0] += (VT)a[0] * w[0] + (VT)a[3] * w[1] + (VT)a[6] * w[2];
+  acc[1] += (VT)a[1] * w[0] + (VT)a[4] * w[1] + (VT)a[7] * w[2];
+  acc[2] += (VT)a[2] * w[0] + (VT)a[5] * w[1] + (VT)a[8] * w[2];
 }
 
-template <typename MT, typename VT, bool MASK>
-__device__ __forceinline__ void spmv_row(int i, int g, const BsrView<MT> &B, const int *__restrict__ grp,
-                                         const VT *__restrict__ v, VT *acc) {
+// Row i of the product into acc (complete on lane g == 0, which also
+// returns the row's own operand entries in own).
+template <typename MT, typename VT, bool MASK, typename F>
+__device__ __forceinline__ void spmv_row(int i, int g, const BsrView<MT> &B, const int *__restrict__ grp, const F &v,
+                                         VT *acc, VT *own) {
   acc[0] = acc[1] = acc[2] = (VT)0;
+  VT w0[3], w1[3];
   if (i >= 0) {
     const int gi = MASK ? grp[i] : 0;
     const int l0 = B.rp[i], l1 = B.rp[i + 1], u0 = B.up[i], u1 = B.up[i + 1];
@@ -563,34 +587,44 @@ __device__ __forceinline__ void spmv_row(int i, int g, const BsrView<MT> &B, con
     int k = l0 + g;
     for (; k + kG < l1; k += 2 * kG) {
       const int j0 = B.ci[k], j1 = B.ci[k + kG];
-      if (!MASK || grp[j0] == gi) blk_mv<MT, VT>(B.val + (size_t)9 * k, v, j0, acc);
-      if (!MASK || grp[j1] == gi) blk_mv<MT, VT>(B.val + (size_t)9 * (k + kG), v, j1, acc);
+      v.load(j0, w0);
+      v.load(j1, w1);
+      if (!MASK || grp[j0] == gi) blk_mv<MT, VT>(B.val + (size_t)9 * k, w0, acc);
+      if (!MASK || grp[j1] == gi) blk_mv<MT, VT>(B.val + (size_t)9 * (k + kG), w1, acc);
     }
     if (k < l1) {
       const int j = B.ci[k];
-      if (!MASK || grp[j] == gi) blk_mv<MT, VT>(B.val + (size_t)9 * k, v, j, acc);
+      v.load(j, w0);
+      if (!MASK || grp[j] == gi) blk_mv<MT, VT>(B.val + (size_t)9 * k, w0, acc);
     }
     // the blocks of column i, stored in the rows below, applied transposed
     int e = u0 + g;
     for (; e + kG < u1; e += 2 * kG) {
       const int2 x0 = B.ue[e], x1 = B.ue[e + kG];
-      if (!MASK || grp[x0.x] == gi) blk_mtv<MT, VT>(B.val + (size_t)9 * x0.y, v, x0.x, acc);
-      if (!MASK || grp[x1.x] == gi) blk_mtv<MT, VT>(B.val + (size_t)9 * x1.y, v, x1.x, acc);
+      v.load(x0.x, w0);
+      v.load(x1.x, w1);
+      if (!MASK || grp[x0.x] == gi) blk_mtv<MT, VT>(B.val + (size_t)9 * x0.y, w0, acc);
+      if (!MASK || grp[x1.x] == gi) blk_mtv<MT, VT>(B.val + (size_t)9 * x1.y, w1, acc);
     }
     if (e < u1) {
       const int2 x = B.ue[e];
-      if (!MASK || grp[x.x] == gi) blk_mtv<MT, VT>(B.val + (size_t)9 * x.y, v, x.x, acc);
+      v.load(x.x, w0);
+      if (!MASK || grp[x.x] == gi) blk_mtv<MT, VT>(B.val + (size_t)9 * x.y, w0, acc);
     }
     for (int c = B.cp[i] + g; c < B.cp[i + 1]; c += kG) {
       const int j = B.cc[c];
-      if (!MASK || grp[j] == gi) blk_mv<MT, VT>(B.pblk + (size_t)9 * B.cs[c], v, j, acc);
+      v.load(j, w0);
+      if (!MASK || grp[j] == gi) blk_mv<MT, VT>(B.pblk + (size_t)9 * B.cs[c], w0, acc);
     }
   }
 #pragma unroll
   for (int o = kG / 2; o > 0; o >>= 1)
 #pragma unroll
     for (int c = 0; c < 3; ++c) acc[c] += __shfl_xor(acc[c], o, kG);
-  if (i >= 0 && g == 0) blk_mv<MT, VT>(B.D + (size_t)9 * i, v, i, acc);
+  if (i >= 0 && g == 0) {
+    v.load(i, own);
+    blk_mv<MT, VT>(B.D + (size_t)9 * i, own, acc);
+  }
 }
 
 template <typename MT, typename VT, bool MASK>
@@ -598,8 +632,8 @@ __global__ __launch_bounds__(kBS) void k_spmv(int N, BsrView<MT> B, const int *_
                                               const VT *__restrict__ v, VT *__restrict__ out) {
   long t = (long)xcd_tile() * blockDim.x + threadIdx.x;
   int i = (int)(t / kG), g = (int)(t % kG);
-  VT acc[3];
-  spmv_row<MT, VT, MASK>(i < N ? i : -1, g, B, grp, v, acc);
+  VT acc[3], own[3];
+  spmv_row<MT, VT, MASK>(i < N ? i : -1, g, B, grp, VecPlain<VT>{v}, acc, own);
   if (i < N && g == 0) {
     out[3 * i] = acc[0];
     out[3 * i + 1] = acc[1];
@@ -633,17 +667,24 @@ double spmv_bytes(const Scene &s) {
   return (nL + nC) * (9.0 * w + 4.0) + N * 9.0 * w + 4.0 * N + 3.0 * N * w + 3.0 * N * w;
 }
 
+double cg_product_bytes(const Scene &s) {
+  // the PCG product launch also reads z and writes the new direction p
+  double w = s.mixed ? 4.0 : 8.0;
+  return spmv_bytes(s) + 6.0 * (double)s.N * w;
+}
+
 // ----------------------------------------------------------------- PCG
 // No kernel here fences or counts tickets: a kernel writes per-block
 // partial sums, and the next kernel (a kernel boundary orders the writes)
 // re-sums them in a fixed order, so every scalar is bit-reproducible.
 //
-// Global solve, three launches per iteration k+1 (k completed):
-//   cg_spmv   q = A p, partial p.q
-//   cg_update alpha = rz_k / sum(p.q) in every block; x += alpha p,
-//             r -= alpha q, z = D^{-1} r, partials r.z, r.r
-//   cg_dir    beta = sum(r.z) / rz_k, stopping rules, p = z + beta p;
-//             block 0 writes the state after iteration k+1
+// Global solve, two launches per iteration k:
+//   cg_dir_spmv  state after iteration k from the previous partials
+//                (beta_k = rz_k / rz_{k-1}, stopping rules; block 0 writes
+//                it), p_k = z + beta_k p_{k-1} formed where it is read,
+//                q = A p_k, partial p_k.q
+//   cg_update    alpha = rz_k / sum(p.q) in every block; x += alpha p_k,
+//                r -= alpha q, z = D^{-1} r, partials r.z, r.r
 // The state after iteration k lives in slot k & 1 (the host passes k), so
 // the slot being written is never the slot being read.
 //
@@ -752,15 +793,14 @@ __device__ __forceinline__ void spmv_partial(int N, const BsrView<MT> &B, const 
   double vals[1] = {0.0};
   int bin = -1;
   int i = (int)(t / kG), g = (int)(t % kG);
-  VT acc[3];
-  spmv_row<MT, VT, (NB > 1)>(i < N ? i : -1, g, B, grp, p, acc);
+  VT acc[3], own[3];
+  spmv_row<MT, VT, (NB > 1)>(i < N ? i : -1, g, B, grp, VecPlain<VT>{p}, acc, own);
   if (i < N && g == 0) {
     q[3 * i] = acc[0];
     q[3 * i + 1] = acc[1];
     q[3 * i + 2] = acc[2];
     bin = bin_of<NB>(grp, i);
-    vals[0] = (double)p[3 * i] * (double)acc[0] + (double)p[3 * i + 1] * (double)acc[1] +
-              (double)p[3 * i + 2] * (double)acc[2];
+    vals[0] = (double)own[0] * (double)acc[0] + (double)own[1] * (double)acc[1] + (double)own[2] * (double)acc[2];
   }
   block_partials<NB, 1>(bin, vals, part, tile);
 }
@@ -797,13 +837,116 @@ __device__ __forceinline__ void update_partial(int N, int i, const uint8_t *fr, 
 }
 
 // ---- global solve
-template <typename MT, typename VT>
-__global__ __launch_bounds__(kBS) void k_cg_spmv(int N, int k, BsrView<MT> B, const VT *__restrict__ p,
-                                                 VT *__restrict__ q, const CgCtl *ctl, double *part) {
-  if (ctl->stop || ctl->slot[k & 1].done) return;
-  spmv_partial<MT, VT, 1>(N, B, nullptr, p, q, part);
+// Sums of up to three partial arrays with every thread of the block: each
+// thread issues all of its loads before adding them (in a fixed order), then
+// a fixed shuffle tree per wave and the waves in order.  The partial arrays
+// here hold a few hundred entries, so one round of loads covers them.
+template <int NS>
+__device__ void block_sums(const double *const *src, const int *n, double *out) {
+  constexpr int kU = 4;
+  __shared__ double sh[NS][kBS / 64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double acc[NS];
+#pragma unroll
+  for (int m = 0; m < NS; ++m) {
+    acc[m] = 0.0;
+    for (int j0 = threadIdx.x; j0 < n[m]; j0 += kU * kBS) {
+      double v[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) v[u] = j0 + u * kBS < n[m] ? src[m][j0 + u * kBS] : 0.0;
+#pragma unroll
+      for (int u = 0; u < kU; ++u) acc[m] += v[u];
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < NS; ++m) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc[m] += __shfl_down(acc[m], o, 64);
+    if (lane == 0) sh[m][w] = acc[m];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < NS; ++m) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < kBS / 64; ++q) t += sh[m][q];
+    out[m] = t;
+  }
+  __syncthreads();  // sh is reused by the next call
 }
 
+// Iteration k, first launch.  Unless this is the first iteration (previous
+// slot marked it = -1, state 0 written by the initialisation), forms the
+// state after iteration k from the previous partials and applies the
+// stopping rules (App. B: relative residual, stagnation over the window, cap;
+// p.q <= 0 is a breakdown); block 0 stores it in slot k & 1.  Then
+// p_k = z + beta_k p_{k-1} (the row owner stores it), q = A p_k and the
+// partial p_k.q.  p is double-buffered (p_new never aliases p_old) and so is
+// the p.q partial array (this launch reads one and writes the other).
+template <typename MT, typename VT>
+__global__ __launch_bounds__(kBS) void k_cg_dir_spmv(int N, int k, BsrView<MT> B, const VT *__restrict__ z,
+                                                     const VT *__restrict__ p_old, VT *__restrict__ p_new,
+                                                     VT *__restrict__ q, CgCtl *ctl, const double *part, int nb,
+                                                     const double *part_pq_prev, double *part_pq) {
+  if (ctl->stop) return;
+  const CgSlot &prev = ctl->slot[(k - 1) & 1];
+  double beta = 0.0;
+  const VT *pold = p_old;
+  if (prev.it < 0) {
+    if (ctl->slot[k & 1].done) return;
+    pold = z;  // p_0 = z_0 (beta = 0 must not meet an unset buffer)
+  } else {
+    if (prev.done) return;
+    double t[3];
+    const double *src[3] = {part, part + nb, part_pq_prev};
+    const int cnt[3] = {nb, nb, (int)gridDim.x};
+    block_sums<3>(src, cnt, t);
+    const double rz = t[0], rr = t[1], pq = t[2];
+    const int it = prev.it + 1;
+    const double rn = sqrt(rr);
+    int done = PCG_RUN;
+    double rmin = prev.rmin;
+    int it_min = prev.it_min;
+    if (!(pq > 0.0)) done = PCG_BREAKDOWN;
+    else if (rr <= ctl->tol2 * ctl->ref2) done = PCG_CONVERGED;
+    if (rn < rmin) { rmin = rn; it_min = it; }
+    if (!done && ctl->stall > 0 && it - it_min >= ctl->stall) done = PCG_STALLED;
+    if (!done && it >= ctl->max_it) done = PCG_CAPPED;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      CgSlot &o = ctl->slot[k & 1];
+      o.rz = rz;
+      o.rr = rr;
+      o.rmin = rmin;
+      o.rnorm = rn;
+      o.it = it;
+      o.it_min = it_min;
+      o.done = done;
+      if (done) ctl->stop = 1;  // later launches exit at once
+    }
+    if (done) return;
+    beta = prev.rz != 0.0 ? rz / prev.rz : 0.0;
+  }
+  const int tile = xcd_tile();
+  long t = (long)tile * blockDim.x + threadIdx.x;
+  int i = (int)(t / kG), g = (int)(t % kG);
+  double vals[1] = {0.0};
+  int bin = -1;
+  VT acc[3], own[3];
+  spmv_row<MT, VT, false>(i < N ? i : -1, g, B, nullptr, VecDir<VT>{z, pold, beta}, acc, own);
+  if (i < N && g == 0) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      p_new[3 * i + c] = own[c];
+      q[3 * i + c] = acc[c];
+    }
+    bin = 0;
+    vals[0] = (double)own[0] * (double)acc[0] + (double)own[1] * (double)acc[1] + (double)own[2] * (double)acc[2];
+  }
+  block_partials<1, 1>(bin, vals, part_pq, tile);
+}
+
+// Iteration k, second launch: alpha = rz_k / sum(p.q); x += alpha p,
+// r -= alpha q, z = D^{-1} r, partials r.z and r.r.
 template <typename MT, typename VT>
 __global__ __launch_bounds__(kBS) void k_cg_update(int N, int k, const uint8_t *__restrict__ fr,
                                                    const MT *__restrict__ Dinv, const VT *__restrict__ p,
@@ -812,55 +955,12 @@ __global__ __launch_bounds__(kBS) void k_cg_update(int N, int k, const uint8_t *
                                                    const double *part_pq, int nb_pq, double *part) {
   const CgSlot &s = ctl->slot[k & 1];
   if (ctl->stop || s.done) return;
-  __shared__ double tot[1][1];
-  sum_blocks<1, 1>(part_pq, nb_pq, tot);
-  double pq = tot[0][0];
-  double al = pq > 0.0 ? s.rz / pq : 0.0;  // breakdown handled in k_cg_dir
+  double pq;
+  const double *src[1] = {part_pq};
+  const int cnt[1] = {nb_pq};
+  block_sums<1>(src, cnt, &pq);
+  double al = pq > 0.0 ? s.rz / pq : 0.0;  // a breakdown is recorded by the next launch
   update_partial<MT, VT, 1>(N, blockIdx.x * blockDim.x + threadIdx.x, fr, Dinv, nullptr, p, q, x, r, z, &al, part);
-}
-
-template <typename VT>
-__global__ __launch_bounds__(kBS) void k_cg_dir(int N, int k, const VT *__restrict__ z, VT *__restrict__ p, CgCtl *ctl,
-                                                const double *part_pq, int nb_pq, const double *part) {
-  const CgSlot &s = ctl->slot[k & 1];
-  if (ctl->stop || s.done) return;
-  __shared__ double tot[2][1];
-  __shared__ double tpq[1][1];
-  sum_blocks<1, 2>(part, gridDim.x, tot);
-  sum_blocks<1, 1>(part_pq, nb_pq, tpq);
-  double rz = tot[0][0], rr = tot[1][0];
-  int it = s.it + 1;
-  double rn = sqrt(rr);
-  int done = PCG_RUN;
-  double rmin = s.rmin;
-  int it_min = s.it_min;
-  if (!(tpq[0][0] > 0.0)) done = PCG_BREAKDOWN;
-  else if (rr <= ctl->tol2 * ctl->ref2) done = PCG_CONVERGED;
-  if (rn < rmin) { rmin = rn; it_min = it; }
-  if (!done && ctl->stall > 0 && it - it_min >= ctl->stall) done = PCG_STALLED;
-  if (!done && it >= ctl->max_it) done = PCG_CAPPED;
-  if (!done) {
-    double be = s.rz != 0.0 ? rz / s.rz : 0.0;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < N) {
-#pragma unroll
-      for (int c = 0; c < 3; ++c) p[3 * i + c] = (VT)((double)z[3 * i + c] + be * (double)p[3 * i + c]);
-    }
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    CgSlot &o = ctl->slot[(k + 1) & 1];
-    o.rz = rz;
-    o.rr = rr;
-    o.rmin = rmin;
-    o.rnorm = rn;
-    o.it = it;
-    o.it_min = it_min;
-    o.done = done;
-    // Later launches read the other parity slot, which still holds an older
-    // running state; the stop flag keeps them from updating x again.  Blocks
-    // of this launch that see it early skip only the direction update.
-    if (done) ctl->stop = 1;
-  }
 }
 
 // ---- warm start (per-group bins)
@@ -875,9 +975,10 @@ __global__ __launch_bounds__(kBS) void k_w_spmv(int N, BsrView<MT> B, const int 
 // One block per group bin: the sum of that bin's partials (bin-major
 // layout, contiguous), reduced in a fixed order and seen by every thread.
 __device__ double bin_sum(const double *part, int nbk, int k) {
-  double acc = 0.0;
-  for (int j = threadIdx.x; j < nbk; j += blockDim.x) acc += part[(size_t)k * nbk + j];
-  return block_reduce(acc, OpSum(), 0.0);
+  const double *src[1] = {part + (size_t)k * nbk};
+  double out;
+  block_sums<1>(src, &nbk, &out);
+  return out;
 }
 
 __global__ void k_w_alpha(int nbk, WarmCtl *ctl, const double *part) {
@@ -1142,26 +1243,37 @@ template <typename MT, typename VT>
 static int cg_run(Scene &s, const double *rhs, double *xsol, double tol, double ref2, int max_iters, bool start,
                   bool resume, int *iters_out, double *rnorm_out) {
   int N = s.N, nb = blocks_for(N, kBS), nbs = spmv_grid(N);
-  if (s.partial.grow((size_t)(nbs + 3 * nb) * sizeof(double)) || s.pcg_ctl.grow(sizeof(CgCtl))) return BAL_E_OOM;
-  double *part_pq = s.partial.as<double>(), *part = part_pq + (size_t)nbs;
+  if (s.partial.grow((size_t)(2 * nbs + 3 * nb) * sizeof(double)) || s.pcg_ctl.grow(sizeof(CgCtl)) ||
+      s.pv2.grow((size_t)3 * N * sizeof(VT)))
+    return BAL_E_OOM;
+  double *pq0 = s.partial.as<double>(), *pq1 = pq0 + (size_t)nbs, *part = pq1 + (size_t)nbs;
   CgCtl *ctl = s.pcg_ctl.as<CgCtl>();
   CgCtl *h = s.pin.as<CgCtl>();
-  VT *p = static_cast<VT *>(s.pv.p), *q = static_cast<VT *>(s.q.p), *z = static_cast<VT *>(s.z.p);
+  VT *p0 = static_cast<VT *>(s.pv.p), *p1 = static_cast<VT *>(s.pv2.p), *q = static_cast<VT *>(s.q.p),
+     *z = static_cast<VT *>(s.z.p);
   const BsrView<MT> B = bsr_view<MT>(s);
   const MT *Dinv = static_cast<const MT *>(s.Dinv.p);
   double *r = s.r.as<double>();
   int k;
   if (resume) {
-    // continue the same Krylov sequence for max_iters more iterations, tolerance off
+    // continue the same Krylov sequence for max_iters more iterations, tolerance off:
+    // the stopped state k is recomputed from the partials it was made of, with the
+    // stagnation window restarted
     hipMemcpyAsync(h, ctl, sizeof(CgCtl), hipMemcpyDeviceToHost, s.stream);
     hipStreamSynchronize(s.stream);
     int cur = h->slot[0].it >= h->slot[1].it ? 0 : 1;
     CgSlot sl = h->slot[cur];
     k = sl.it;
     if (sl.done == PCG_BREAKDOWN) { *iters_out = k; *rnorm_out = sl.rnorm; return BAL_E_NO_CONVERGENCE; }
-    sl.done = PCG_RUN;
-    sl.it_min = sl.it;
-    h->slot[k & 1] = sl;
+    if (k == 0) {
+      h->slot[0].done = PCG_RUN;
+      h->slot[0].it_min = 0;
+      h->slot[0].rmin = h->slot[0].rnorm;
+    } else {
+      CgSlot &pv = h->slot[(k - 1) & 1];
+      pv.done = PCG_RUN;
+      pv.rmin = INFINITY;
+    }
     h->max_it = k + max_iters;
     h->tol2 = 0.0;
     h->stop = 0;
@@ -1174,22 +1286,25 @@ static int cg_run(Scene &s, const double *rhs, double *xsol, double tol, double 
   }
   const int chunk = 16;
   auto launch_iter = [&](int kk, hipEvent_t e0, hipEvent_t e1) {
+    VT *pnew = (kk & 1) ? p1 : p0, *pold = (kk & 1) ? p0 : p1;
+    double *ppq = (kk & 1) ? pq1 : pq0, *ppq_prev = (kk & 1) ? pq0 : pq1;
     // timed launches carry their own start/stop events (kernel execution only)
     if (e0)
-      hipExtLaunchKernelGGL((k_cg_spmv<MT, VT>), dim3(nbs), dim3(kBS), 0, s.stream, e0, e1, 0, N, kk, B, p, q, ctl,
-                            part_pq);
+      hipExtLaunchKernelGGL((k_cg_dir_spmv<MT, VT>), dim3(nbs), dim3(kBS), 0, s.stream, e0, e1, 0, N, kk, B, z, pold,
+                            pnew, q, ctl, part, nb, ppq_prev, ppq);
     else
-      hipLaunchKernelGGL((k_cg_spmv<MT, VT>), dim3(nbs), dim3(kBS), 0, s.stream, N, kk, B, p, q, ctl, part_pq);
-    hipLaunchKernelGGL((k_cg_update<MT, VT>), dim3(nb), dim3(kBS), 0, s.stream, N, kk, s.freev.as<uint8_t>(), Dinv, p,
-                       q, xsol, r, z, ctl, part_pq, nbs, part);
-    hipLaunchKernelGGL((k_cg_dir<VT>), dim3(nb), dim3(kBS), 0, s.stream, N, kk, z, p, ctl, part_pq, nbs, part);
+      hipLaunchKernelGGL((k_cg_dir_spmv<MT, VT>), dim3(nbs), dim3(kBS), 0, s.stream, N, kk, B, z, pold, pnew, q, ctl,
+                         part, nb, ppq_prev, ppq);
+    hipLaunchKernelGGL((k_cg_update<MT, VT>), dim3(nb), dim3(kBS), 0, s.stream, N, kk, s.freev.as<uint8_t>(), Dinv,
+                       pnew, q, xsol, r, z, ctl, ppq, nbs, part);
   };
   // the kernels use only k & 1, so one capture serves every chunk that starts
-  // at an even k.  Kernel timing brackets every SpMV with events, which a
+  // at an even k.  Kernel timing brackets every product with events, which a
   // captured graph does not time: timed solves launch eagerly.
   std::vector<uintptr_t> sig = bsr_sig(B);
-  sig.insert(sig.end(), {(uintptr_t)p, (uintptr_t)q, (uintptr_t)ctl, (uintptr_t)part_pq, (uintptr_t)s.freev.p,
-                         (uintptr_t)Dinv, (uintptr_t)xsol, (uintptr_t)r, (uintptr_t)z, (uintptr_t)N});
+  sig.insert(sig.end(), {(uintptr_t)p0, (uintptr_t)p1, (uintptr_t)q, (uintptr_t)ctl, (uintptr_t)pq0,
+                         (uintptr_t)s.freev.p, (uintptr_t)Dinv, (uintptr_t)xsol, (uintptr_t)r, (uintptr_t)z,
+                         (uintptr_t)N});
   for (;;) {
     bool graphed = false;
     const int first = k;
