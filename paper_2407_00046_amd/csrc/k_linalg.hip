@@ -574,45 +574,63 @@ __device__ __forceinline__ void blk_mtv(const MT *__restrict__ a, const VT *w, V
 }
 
 // Row i of the product into acc (complete on lane g == 0, which also
-// returns the row's own operand entries in own).
+// returns the row's own operand entries in own).  The row's own blocks and
+// the transposed blocks of its column form one list of nl + nu entries; a
+// lane takes entries g, g + kG, ... and handles kU of them per pass: first
+// all their indices, then all their blocks and operand entries, then the
+// arithmetic, so that a typical row costs two rounds of memory latency.
+constexpr int kU = 3;
+
 template <typename MT, typename VT, bool MASK, typename F>
 __device__ __forceinline__ void spmv_row(int i, int g, const BsrView<MT> &B, const int *__restrict__ grp, const F &v,
                                          VT *acc, VT *own) {
   acc[0] = acc[1] = acc[2] = (VT)0;
-  VT w0[3], w1[3];
   if (i >= 0) {
     const int gi = MASK ? grp[i] : 0;
-    const int l0 = B.rp[i], l1 = B.rp[i + 1], u0 = B.up[i], u1 = B.up[i + 1];
-    // the row's own blocks, two per pass so that both gathers are in flight together
-    int k = l0 + g;
-    for (; k + kG < l1; k += 2 * kG) {
-      const int j0 = B.ci[k], j1 = B.ci[k + kG];
-      v.load(j0, w0);
-      v.load(j1, w1);
-      if (!MASK || grp[j0] == gi) blk_mv<MT, VT>(B.val + (size_t)9 * k, w0, acc);
-      if (!MASK || grp[j1] == gi) blk_mv<MT, VT>(B.val + (size_t)9 * (k + kG), w1, acc);
-    }
-    if (k < l1) {
-      const int j = B.ci[k];
-      v.load(j, w0);
-      if (!MASK || grp[j] == gi) blk_mv<MT, VT>(B.val + (size_t)9 * k, w0, acc);
-    }
-    // the blocks of column i, stored in the rows below, applied transposed
-    int e = u0 + g;
-    for (; e + kG < u1; e += 2 * kG) {
-      const int2 x0 = B.ue[e], x1 = B.ue[e + kG];
-      v.load(x0.x, w0);
-      v.load(x1.x, w1);
-      if (!MASK || grp[x0.x] == gi) blk_mtv<MT, VT>(B.val + (size_t)9 * x0.y, w0, acc);
-      if (!MASK || grp[x1.x] == gi) blk_mtv<MT, VT>(B.val + (size_t)9 * x1.y, w1, acc);
-    }
-    if (e < u1) {
-      const int2 x = B.ue[e];
-      v.load(x.x, w0);
-      if (!MASK || grp[x.x] == gi) blk_mtv<MT, VT>(B.val + (size_t)9 * x.y, w0, acc);
+    const int l0 = B.rp[i], nl = B.rp[i + 1] - l0, u0 = B.up[i], nt = nl + B.up[i + 1] - u0;
+    for (int t = g; t < nt; t += kU * kG) {
+      int j[kU], k[kU];
+      bool tr[kU], on[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int tt = t + u * kG;
+        on[u] = tt < nt;
+        tr[u] = tt >= nl;
+        j[u] = i;
+        k[u] = 0;
+        if (on[u]) {
+          if (!tr[u]) {
+            k[u] = l0 + tt;
+            j[u] = B.ci[k[u]];
+          } else {
+            const int2 e = B.ue[u0 + tt - nl];
+            j[u] = e.x;
+            k[u] = e.y;
+          }
+        }
+      }
+      MT a[kU][9];
+      VT w[kU][3];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        if (on[u]) {
+          const MT *src = B.val + (size_t)9 * k[u];
+#pragma unroll
+          for (int c = 0; c < 9; ++c) a[u][c] = src[c];
+          v.load(j[u], w[u]);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        if (on[u] && (!MASK || grp[j[u]] == gi)) {
+          if (tr[u]) blk_mtv<MT, VT>(a[u], w[u], acc);
+          else blk_mv<MT, VT>(a[u], w[u], acc);
+        }
+      }
     }
     for (int c = B.cp[i] + g; c < B.cp[i + 1]; c += kG) {
       const int j = B.cc[c];
+      VT w0[3];
       v.load(j, w0);
       if (!MASK || grp[j] == gi) blk_mv<MT, VT>(B.pblk + (size_t)9 * B.cs[c], w0, acc);
     }
