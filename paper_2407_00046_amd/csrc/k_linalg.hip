@@ -579,56 +579,89 @@ __device__ __forceinline__ void blk_mtv(const MT *__restrict__ a, const VT *w, V
 // lane takes entries g, g + kG, ... and handles kU of them per pass: first
 // all their indices, then all their blocks and operand entries, then the
 // arithmetic, so that a typical row costs two rounds of memory latency.
+// `pre` runs (on every thread of the block) after the first pass's index
+// and block loads and the diagonal block load are issued and before any
+// operand entry is read; it may set up the operand (the CG direction's beta)
+// and returns false to abandon the product.
 constexpr int kU = 3;
 
-template <typename MT, typename VT, bool MASK, typename F>
-__device__ __forceinline__ void spmv_row(int i, int g, const BsrView<MT> &B, const int *__restrict__ grp, const F &v,
-                                         VT *acc, VT *own) {
-  acc[0] = acc[1] = acc[2] = (VT)0;
-  if (i >= 0) {
-    const int gi = MASK ? grp[i] : 0;
-    const int l0 = B.rp[i], nl = B.rp[i + 1] - l0, u0 = B.up[i], nt = nl + B.up[i + 1] - u0;
-    for (int t = g; t < nt; t += kU * kG) {
-      int j[kU], k[kU];
-      bool tr[kU], on[kU];
+template <typename MT>
+struct RowBatch {
+  int j[kU], k[kU];
+  bool tr[kU], on[kU];
+  MT a[kU][9];
+};
+
+template <typename MT>
+__device__ __forceinline__ void row_fetch(int i, int t, int l0, int nl, int u0, int nt, const BsrView<MT> &B,
+                                          RowBatch<MT> &rb) {
 #pragma unroll
-      for (int u = 0; u < kU; ++u) {
-        const int tt = t + u * kG;
-        on[u] = tt < nt;
-        tr[u] = tt >= nl;
-        j[u] = i;
-        k[u] = 0;
-        if (on[u]) {
-          if (!tr[u]) {
-            k[u] = l0 + tt;
-            j[u] = B.ci[k[u]];
-          } else {
-            const int2 e = B.ue[u0 + tt - nl];
-            j[u] = e.x;
-            k[u] = e.y;
-          }
-        }
-      }
-      MT a[kU][9];
-      VT w[kU][3];
-#pragma unroll
-      for (int u = 0; u < kU; ++u) {
-        if (on[u]) {
-          const MT *src = B.val + (size_t)9 * k[u];
-#pragma unroll
-          for (int c = 0; c < 9; ++c) a[u][c] = src[c];
-          v.load(j[u], w[u]);
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < kU; ++u) {
-        if (on[u] && (!MASK || grp[j[u]] == gi)) {
-          if (tr[u]) blk_mtv<MT, VT>(a[u], w[u], acc);
-          else blk_mv<MT, VT>(a[u], w[u], acc);
-        }
+  for (int u = 0; u < kU; ++u) {
+    const int tt = t + u * kG;
+    rb.on[u] = tt < nt;
+    rb.tr[u] = tt >= nl;
+    rb.j[u] = i;
+    rb.k[u] = 0;
+    if (rb.on[u]) {
+      if (!rb.tr[u]) {
+        rb.k[u] = l0 + tt;
+        rb.j[u] = B.ci[rb.k[u]];
+      } else {
+        const int2 e = B.ue[u0 + tt - nl];
+        rb.j[u] = e.x;
+        rb.k[u] = e.y;
       }
     }
-    for (int c = B.cp[i] + g; c < B.cp[i + 1]; c += kG) {
+  }
+#pragma unroll
+  for (int u = 0; u < kU; ++u)
+    if (rb.on[u]) {
+      const MT *src = B.val + (size_t)9 * rb.k[u];
+#pragma unroll
+      for (int c = 0; c < 9; ++c) rb.a[u][c] = src[c];
+    }
+}
+
+template <typename MT, typename VT, bool MASK, typename F, typename Pre>
+__device__ __forceinline__ bool spmv_row_pre(int i, int g, const BsrView<MT> &B, const int *__restrict__ grp, F &v,
+                                             Pre &&pre, VT *acc, VT *own) {
+  acc[0] = acc[1] = acc[2] = (VT)0;
+  int l0 = 0, nl = 0, u0 = 0, nt = 0, c0 = 0, c1 = 0, gi = 0;
+  RowBatch<MT> rb;
+  MT dblk[9];
+  if (i >= 0) {
+    l0 = B.rp[i];
+    nl = B.rp[i + 1] - l0;
+    u0 = B.up[i];
+    nt = nl + B.up[i + 1] - u0;
+    c0 = B.cp[i];
+    c1 = B.cp[i + 1];
+    if (MASK) gi = grp[i];
+    row_fetch<MT>(i, g, l0, nl, u0, nt, B, rb);
+    if (g == 0) {
+#pragma unroll
+      for (int c = 0; c < 9; ++c) dblk[c] = B.D[(size_t)9 * i + c];
+    }
+  }
+  if (!pre()) return false;
+  if (i >= 0) {
+    for (int t = g;;) {
+      VT w[kU][3];
+#pragma unroll
+      for (int u = 0; u < kU; ++u)
+        if (rb.on[u]) v.load(rb.j[u], w[u]);
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        if (rb.on[u] && (!MASK || grp[rb.j[u]] == gi)) {
+          if (rb.tr[u]) blk_mtv<MT, VT>(rb.a[u], w[u], acc);
+          else blk_mv<MT, VT>(rb.a[u], w[u], acc);
+        }
+      }
+      t += kU * kG;
+      if (t >= nt) break;
+      row_fetch<MT>(i, t, l0, nl, u0, nt, B, rb);
+    }
+    for (int c = c0 + g; c < c1; c += kG) {
       const int j = B.cc[c];
       VT w0[3];
       v.load(j, w0);
@@ -641,8 +674,15 @@ __device__ __forceinline__ void spmv_row(int i, int g, const BsrView<MT> &B, con
     for (int c = 0; c < 3; ++c) acc[c] += __shfl_xor(acc[c], o, kG);
   if (i >= 0 && g == 0) {
     v.load(i, own);
-    blk_mv<MT, VT>(B.D + (size_t)9 * i, own, acc);
+    blk_mv<MT, VT>(dblk, own, acc);
   }
+  return true;
+}
+
+template <typename MT, typename VT, bool MASK, typename F>
+__device__ __forceinline__ void spmv_row(int i, int g, const BsrView<MT> &B, const int *__restrict__ grp, F v,
+                                         VT *acc, VT *own) {
+  spmv_row_pre<MT, VT, MASK>(i, g, B, grp, v, [] { return true; }, acc, own);
 }
 
 template <typename MT, typename VT, bool MASK>
@@ -908,18 +948,21 @@ __global__ __launch_bounds__(kBS) void k_cg_dir_spmv(int N, int k, BsrView<MT> B
                                                      const double *part_pq_prev, double *part_pq) {
   if (ctl->stop) return;
   const CgSlot &prev = ctl->slot[(k - 1) & 1];
-  double beta = 0.0;
-  const VT *pold = p_old;
-  if (prev.it < 0) {
-    if (ctl->slot[k & 1].done) return;
-    pold = z;  // p_0 = z_0 (beta = 0 must not meet an unset buffer)
-  } else {
-    if (prev.done) return;
-    double t[3];
+  const bool first = prev.it < 0;
+  if (first ? ctl->slot[k & 1].done : prev.done) return;
+  const int tile = xcd_tile();
+  long t = (long)tile * blockDim.x + threadIdx.x;
+  int i = (int)(t / kG), g = (int)(t % kG);
+  VecDir<VT> dir{z, first ? z : p_old, 0.0};  // p_0 = z_0: beta = 0 must not meet an unset buffer
+  // the state after iteration k and beta_k, from the previous partials; runs
+  // while the row's first index and block loads are in flight
+  auto state = [&]() -> bool {
+    if (first) return true;
+    double tv[3];
     const double *src[3] = {part, part + nb, part_pq_prev};
     const int cnt[3] = {nb, nb, (int)gridDim.x};
-    block_sums<3>(src, cnt, t);
-    const double rz = t[0], rr = t[1], pq = t[2];
+    block_sums<3>(src, cnt, tv);
+    const double rz = tv[0], rr = tv[1], pq = tv[2];
     const int it = prev.it + 1;
     const double rn = sqrt(rr);
     int done = PCG_RUN;
@@ -941,16 +984,13 @@ __global__ __launch_bounds__(kBS) void k_cg_dir_spmv(int N, int k, BsrView<MT> B
       o.done = done;
       if (done) ctl->stop = 1;  // later launches exit at once
     }
-    if (done) return;
-    beta = prev.rz != 0.0 ? rz / prev.rz : 0.0;
-  }
-  const int tile = xcd_tile();
-  long t = (long)tile * blockDim.x + threadIdx.x;
-  int i = (int)(t / kG), g = (int)(t % kG);
+    dir.beta = prev.rz != 0.0 ? rz / prev.rz : 0.0;
+    return !done;
+  };
   double vals[1] = {0.0};
   int bin = -1;
   VT acc[3], own[3];
-  spmv_row<MT, VT, false>(i < N ? i : -1, g, B, nullptr, VecDir<VT>{z, pold, beta}, acc, own);
+  if (!spmv_row_pre<MT, VT, false>(i < N ? i : -1, g, B, nullptr, dir, state, acc, own)) return;
   if (i < N && g == 0) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -973,12 +1013,47 @@ __global__ __launch_bounds__(kBS) void k_cg_update(int N, int k, const uint8_t *
                                                    const double *part_pq, int nb_pq, double *part) {
   const CgSlot &s = ctl->slot[k & 1];
   if (ctl->stop || s.done) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool act = i < N && fr[i];
+  // the node's operands are loaded while the p.q partials are summed
+  double pv[3] = {0.0, 0.0, 0.0}, qv[3] = {0.0, 0.0, 0.0}, xv[3] = {0.0, 0.0, 0.0}, rv[3] = {0.0, 0.0, 0.0};
+  MT d[9];
+  if (act) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      pv[c] = (double)p[3 * i + c];
+      qv[c] = (double)q[3 * i + c];
+      xv[c] = x[3 * i + c];
+      rv[c] = r[3 * i + c];
+    }
+#pragma unroll
+    for (int c = 0; c < 9; ++c) d[c] = Dinv[(size_t)9 * i + c];
+  }
   double pq;
   const double *src[1] = {part_pq};
   const int cnt[1] = {nb_pq};
   block_sums<1>(src, cnt, &pq);
-  double al = pq > 0.0 ? s.rz / pq : 0.0;  // a breakdown is recorded by the next launch
-  update_partial<MT, VT, 1>(N, blockIdx.x * blockDim.x + threadIdx.x, fr, Dinv, nullptr, p, q, x, r, z, &al, part);
+  const double al = pq > 0.0 ? s.rz / pq : 0.0;  // a breakdown is recorded by the next launch
+  double vals[2] = {0.0, 0.0};
+  int bin = -1;
+  if (act) {
+    bin = 0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      x[3 * i + c] = xv[c] + al * pv[c];
+      rv[c] = rv[c] - al * qv[c];
+      r[3 * i + c] = rv[c];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      double zz = (double)d[3 * c] * rv[0] + (double)d[3 * c + 1] * rv[1] + (double)d[3 * c + 2] * rv[2];
+      VT zv = (VT)zz;
+      z[3 * i + c] = zv;
+      vals[0] += rv[c] * (double)zv;
+      vals[1] += rv[c] * rv[c];
+    }
+  }
+  block_partials<1, 2>(bin, vals, part, blockIdx.x);
 }
 
 // ---- warm start (per-group bins)
