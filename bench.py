@@ -32,6 +32,29 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
+def recorded_traffic(kernel):
+    """HBM-side bytes per launch of `kernel` from the PMC summary committed
+    under profiles/ (FETCH_SIZE and WRITE_SIZE scaled by a copy of known
+    size), or None when the kernel's source has changed since the counters
+    were taken."""
+    import glob
+    import hashlib
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        for line in open(path):
+            if not line.startswith("traffic-record: "):
+                continue
+            rec = json.loads(line[len("traffic-record: "):])
+            if rec.get("kernel") != kernel:
+                continue
+            src = os.path.join(ROOT, rec["source"])
+            if not os.path.exists(src):
+                return None
+            if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["source_sha256"]:
+                return None
+            return rec
+    return None
+
+
 def run_precision(sc, precision, steps, warmup, stream):
     """Times `steps` steps after `warmup` steps (PCG replayed as HIP graphs),
     then replays the same steps from the same state with kernel timing on
@@ -179,9 +202,14 @@ def main():
     ach = mixed.get("spmv_gbs")
     roof = None
     if ach:
-        roof = dict(bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS, traffic=None,
-                    kernel="k_cg_dir_spmv<float,float>", bytes_per_launch=mixed["spmv_bytes"],
-                    avg_launch_ms=mixed["spmv_ms_avg"])
+        kern = "k_cg_dir_spmv<float,float>"
+        rec = recorded_traffic(kern)
+        roof = dict(bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
+                    traffic=rec["bytes_per_launch"] if rec else None, kernel=kern,
+                    bytes_per_launch=mixed["spmv_bytes"], avg_launch_ms=mixed["spmv_ms_avg"])
+        if rec:
+            roof["traffic_note"] = (f"PMC on the same kernel source: {rec['bytes_per_launch']} B per launch vs "
+                                    f"{rec['algorithmic_bytes_probe']} B algorithmic on the probe's matrix")
     line = dict(
         metric="s/timestep & PCG iters/s, mixed vs FP64 at 1e-4 tol; BSR SpMV HBM GB/s",
         value=mixed["s_per_step"], unit="s/step", n_gpus=1, steps=args.steps, warmup=args.warmup,
