@@ -494,8 +494,23 @@ class OracleScene:
         d, case = self.distances(x, allp)
         if (d <= 0).any():
             return (np.inf, None) if with_grad else np.inf
-        sigma = st.sigma if st.sigma is not None else 0.0
         xt = torch.tensor(x, dtype=DT, requires_grad=with_grad)
+        terms = self._objective_terms(xt, y, allp, case, d, st, mu, s, aug)
+        if terms is None:
+            return (np.inf, None) if with_grad else np.inf
+        inertia, elastic, contact = terms
+        total = inertia + elastic + contact
+        if parts:
+            return dict(inertia=float(inertia), elastic=float(elastic), contact=float(contact))
+        if not with_grad:
+            return float(total)
+        total.backward()
+        return float(total.detach()), xt.grad.numpy().copy()
+
+    def _objective_terms(self, xt, y, allp, case, d, st, mu, s, aug):
+        """Inertia, elastic and contact parts of L_sigma at torch positions xt
+        (None if a tet is inverted)."""
+        sigma = st.sigma if st.sigma is not None else 0.0
         free = torch.as_tensor(self.free)
         mass = torch.tensor(self.mass, dtype=DT)
         yt = torch.tensor(y, dtype=DT)
@@ -507,16 +522,25 @@ class OracleScene:
         F = Ds @ self._t_dminv
         J = (F[..., :, 0] * torch.linalg.cross(F[..., :, 1], F[..., :, 2])).sum(-1)
         if (J <= 0).any():
-            return (np.inf, None) if with_grad else np.inf
+            return None
         elastic = (self._t_vol * nh_density_torch(F, self._t_mu, self._t_lam)).sum()
         contact = self._contact_energy_torch(xt, allp, case, d < self.dhat, sigma, mu, s, aug)
-        total = inertia + elastic + contact
-        if parts:
-            return dict(inertia=float(inertia), elastic=float(elastic), contact=float(contact))
-        if not with_grad:
-            return float(total)
-        total.backward()
-        return float(total.detach()), xt.grad.numpy().copy()
+        return inertia, elastic, contact
+
+    def hessian_vector_product(self, x, y, pairs: Pairs, st: ALState, v):
+        """Exact (unprojected) Hessian of L_sigma at x applied to v, (N, 3):
+        the gradient of the same energy definition differentiated once more
+        along v.  Rows and columns of fixed and obstacle vertices are dropped
+        (v is zeroed there and so is the result)."""
+        allp, mu, s, aug = self._merge_pairs(pairs, st)
+        d, case = self.distances(x, allp)
+        xt = torch.tensor(x, dtype=DT, requires_grad=True)
+        terms = self._objective_terms(xt, y, allp, case, d, st, mu, s, aug)
+        total = terms[0] + terms[1] + terms[2]
+        (g,) = torch.autograd.grad(total, xt, create_graph=True)
+        vt = torch.tensor(np.where(self.free[:, None], v, 0.0), dtype=DT)
+        (hv,) = torch.autograd.grad((g * vt).sum(), xt)
+        return np.where(self.free[:, None], hv.numpy(), 0.0)
 
     def gradient_free(self, g_full):
         return g_full[self.free_idx].reshape(-1)

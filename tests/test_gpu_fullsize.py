@@ -1,0 +1,121 @@
+"""GPU vs oracle at the workloads' full sizes, in the benchmark's launch
+configuration (mixed precision, tolerances 1e-4) and in FP64.
+
+At an iterate reached by the GPU's own steps, the library's energy, gradient
+and (unprojected) Hessian-vector product through the C ABI are compared with
+the oracle's plain definitions: the whole vector where the oracle can afford
+the whole scene, sampled rows elsewhere (rows of sampled vertices need only
+the tets around them, so the oracle evaluates a sub-mesh holding every tet
+incident to a sampled vertex; no contact pair is active there).
+"""
+import numpy as np
+import pytest
+
+import scenes
+from oracle import ALState, OracleScene, Params
+from oracle.bal_oracle import Pairs
+from subsets import sub_scene
+
+pytestmark = pytest.mark.gpu
+
+# mixed precision stores the Hessian blocks and runs the product in FP32
+HV_TOL = {"fp64": 1e-10, "mixed": 1e-5}
+
+
+def gpu_scene(sc, prec):
+    from paper_2407_00046_amd import Scene
+    return Scene(sc, precision=prec, newton_rtol=1e-4, pcg_rtol=1e-4, device=0)
+
+
+def compare_whole(sc, prec, n_steps, perturb=0.0):
+    g = gpu_scene(sc, prec)
+    sigma = 0.0
+    for _ in range(n_steps):
+        st = g.step(allow=(0, -7))
+        sigma = st["sigma"]
+    x_t, v_t = g.get_state()
+    nb = x_t.shape[0]
+    obs = np.asarray(sc["obs_pos"]).reshape(-1, 3)
+    rng = np.random.default_rng(11)
+    x_it = x_t + perturb * rng.uniform(-1.0, 1.0, size=x_t.shape) * (sc["fixed"] == 0)[:, None]
+    x = np.concatenate([x_it, obs])
+    v = rng.normal(size=x.shape)
+    e_g, grad_g, na = g.linearize(x, sigma=sigma, project=False)
+    hv_g = g.hessian_apply(v)
+    g.close()
+    o = OracleScene(sc, Params(pair_mode="kdtree"))
+    # the predictor comes from the scene's state (x_t, v_t), not from the iterate
+    y = o.predictor(np.concatenate([x_t, obs]), np.concatenate([v_t, np.zeros_like(obs)]))
+    pairs = o.candidate_pairs(x)
+    d, _ = o.distances(x, pairs)
+    # barrier terms vanish for d >= dhat: keep the pairs inside the support
+    pairs = pairs.take(np.nonzero(d < o.dhat)[0])
+    d = d[d < o.dhat]
+    st = ALState(sigma=sigma if sigma > 0 else None)
+    e_o, grad_o = o.lagrangian(x, y, pairs, st, with_grad=True)
+    grad_o = np.where(o.free[:, None], grad_o, 0.0)
+    hv_o = o.hessian_vector_product(x, y, pairs, st, v)
+    n_act = int((d < o.dhat).sum())
+    print(f"{sc['name']} {prec}: {nb} vertices, {n_act} active pairs, sigma {sigma:.3e}")
+    assert na == n_act
+    assert abs(e_g - e_o) <= 1e-10 * abs(e_o)
+    ge = np.abs(grad_g - grad_o).max() / np.abs(grad_o).max()
+    he = np.abs(hv_g - hv_o).max() / np.abs(hv_o).max()
+    print(f"  gradient rel err {ge:.2e}, Hv rel err {he:.2e}")
+    assert ge <= 1e-10
+    assert he <= HV_TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_stacked_boxes_full_size(prec):
+    compare_whole(scenes.stacked_boxes(n_cubes=8, cells=16, seed=0), prec, 2)
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_beam_full_size(prec):
+    compare_whole(scenes.beam(), prec, 1)
+
+
+def test_chain_net_full_size_near_rest():
+    """At rest the stiff links' elastic forces cancel to rounding of the stress
+    scale (E = 1e9) and the gradient is gravity alone; a 10 um displacement
+    makes the elastic part dominate, as in a step."""
+    compare_whole(scenes.chain_net(), "mixed", 0, perturb=1e-5)
+
+
+def compare_sampled(sc, prec, n_sample=48, perturb=0.0):
+    g = gpu_scene(sc, prec)
+    n = sc["rest_pos"].shape[0]
+    rng = np.random.default_rng(12)
+    xb = sc["x0"] + perturb * rng.uniform(-1.0, 1.0, size=sc["x0"].shape) * (sc["fixed"] == 0)[:, None]
+    x = np.concatenate([xb, np.asarray(sc["obs_pos"]).reshape(-1, 3)])
+    v = rng.normal(size=x.shape)
+    e_g, grad_g, na = g.linearize(x, sigma=0.0, project=False)
+    hv_g = g.hessian_apply(v)
+    g.close()
+    assert na == 0
+    free = np.nonzero(sc["fixed"] == 0)[0]
+    pick = rng.choice(free, size=n_sample, replace=False)
+    sub, used, remap = sub_scene(sc, pick)
+    o = OracleScene(sub, Params())
+    xs = xb[used]
+    y = o.predictor(sc["x0"][used], sc["v0"][used])  # from the scene's state, not the iterate
+    st = ALState()
+    _, grad_o = o.lagrangian(xs, y, Pairs.empty(), st, with_grad=True)
+    hv_o = o.hessian_vector_product(xs, y, Pairs.empty(), st, v[used])
+    rows = remap[pick]
+    ge = np.abs(grad_g[pick] - grad_o[rows]).max() / np.abs(grad_o[rows]).max()
+    he = np.abs(hv_g[pick] - hv_o[rows]).max() / np.abs(hv_o[rows]).max()
+    print(f"{sc['name']} {prec}: {n} vertices, {n_sample} sampled rows over {sub['tets'].shape[0]} tets: "
+          f"gradient rel err {ge:.2e}, Hv rel err {he:.2e}")
+    assert ge <= 1e-10
+    assert he <= HV_TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_spmv_grid_128_sampled_rows(prec):
+    compare_sampled(scenes.spmv_grid(128), prec)
+
+
+def test_chain_net_large_sampled_rows():
+    compare_sampled(scenes.chain_net_large(), "mixed", perturb=1e-5)

@@ -346,6 +346,26 @@ def test_gradient_and_hessian_against_finite_differences():
         assert np.linalg.norm(fdh - hv) <= 1e-5 * np.linalg.norm(hv)
 
 
+def test_hessian_vector_product_against_finite_differences():
+    """The double-backward Hessian-vector product equals central differences
+    of the gradient, and the assembled unprojected Hessian times the vector."""
+    o, x, y, pairs, st = contact_state()
+    H = o.hessian(x, pairs, st, project=False)
+    rng = np.random.default_rng(9)
+    for _ in range(2):
+        v = rng.normal(size=x.shape)
+        hv = o.hessian_vector_product(x, y, pairs, st, v)
+        dx = np.where(o.free[:, None], v, 0.0)
+        eps = 1e-7
+        _, gp = o.lagrangian(x + eps * dx, y, pairs, st, with_grad=True)
+        _, gm = o.lagrangian(x - eps * dx, y, pairs, st, with_grad=True)
+        fd = (o.gradient_free(gp) - o.gradient_free(gm)) / (2 * eps)
+        an = o.gradient_free(hv)
+        assert np.linalg.norm(fd - an) <= 1e-5 * np.linalg.norm(an)
+        assert np.abs(H @ dx[o.free_idx].reshape(-1) - an).max() <= 1e-9 * np.abs(an).max()
+        assert np.all(hv[~o.free] == 0.0)
+
+
 def test_sigma0_is_least_squares_minimiser():
     """sigma0 minimises ||g_E + s g_b||^2 (checked by a scalar minimiser); else the norm-ratio fallback."""
     o, x, y_far, pairs, _ = contact_state()
@@ -460,3 +480,26 @@ def test_kdtree_pair_superset_matches_brute_force():
         need = set(map(int, allp.keys()[d < reach]))
         have = set(map(int, o.near_pairs(x, reach).keys()))
         assert need <= have
+
+
+def test_submesh_rows_equal_full_mesh_rows():
+    """Rows of sampled vertices from the sub-mesh of their incident tets equal
+    the full mesh's rows (the basis of the sampled full-size GPU checks)."""
+    from subsets import sub_scene
+    sc = scenes.spmv_grid(6)
+    o = OracleScene(sc)
+    x = sc["x0"]
+    y = o.predictor(x, sc["v0"])
+    st = ALState()
+    rng = np.random.default_rng(13)
+    v = rng.normal(size=x.shape)
+    _, g_full = o.lagrangian(x, y, o.all_pairs(), st, with_grad=True)
+    hv_full = o.hessian_vector_product(x, y, o.all_pairs(), st, v)
+    pick = rng.choice(x.shape[0], size=12, replace=False)
+    sub, used, remap = sub_scene(sc, pick)
+    os_ = OracleScene(sub)
+    ys = os_.predictor(x[used], sc["v0"][used])
+    _, g_sub = os_.lagrangian(x[used], ys, os_.all_pairs(), st, with_grad=True)
+    hv_sub = os_.hessian_vector_product(x[used], ys, os_.all_pairs(), st, v[used])
+    assert np.abs(g_sub[remap[pick]] - g_full[pick]).max() <= 1e-12 * np.abs(g_full).max()
+    assert np.abs(hv_sub[remap[pick]] - hv_full[pick]).max() <= 1e-12 * np.abs(hv_full).max()
