@@ -318,6 +318,12 @@ class OracleScene:
         self.v = np.concatenate([np.asarray(sc["v0"], dtype=np.float64), np.zeros((m, 3))])
         self.v[~self.free] = 0.0
         self._surface(T, np.asarray(sc["obs_tris"], dtype=np.int64).reshape(-1, 3))
+        # longest CCD sweep of one vertex per pass: 16 mean body surface edge
+        # lengths (at least 4 dhat each); longer steps are halved first
+        # (reading of the memory-limited step halving, Sec. 5.2)
+        be = self.s_edges[(self.s_edges < n).all(1)]
+        mean_edge = float(np.linalg.norm(X[be[:, 0]] - X[be[:, 1]], axis=1).mean()) if len(be) else 1.0
+        self.sweep_len = 16.0 * max(mean_edge, 4.0 * self.dhat)
         self._t_dminv = torch.tensor(self.Dm_inv, dtype=DT)
         self._t_vol = torch.tensor(self.vol, dtype=DT)
         self._set_material()
@@ -712,7 +718,11 @@ class OracleScene:
 
         Per pair: roots of the coplanarity cubic in [-eps, 1+eps] (clamped to
         [0, 1]) are visited in order t1 <= t2 <= t3 with t0 = 0; the first
-        root whose distance d_TOC < eps + dhat is activated, tau = t_{i+1};
+        root whose distance d_TOC < eps + dhat is activated, tau = t_{i+1}
+        (reading: for a pair already closer than dhat at the start of the
+        step, the margin is half its current distance instead of dhat, since
+        with dhat every near miss of two primitives sliding in contact would
+        stop the step at the coplanar time);
         for point-triangle / edge-edge interior cases tau shrinks by 0.9
         while sign sd(tau) != sign sd((t_i + tau) / 2) (reading of the
         reference-frame rule; |sd| <= eps counts as sign 0, so a tau sitting
@@ -751,6 +761,11 @@ class OracleScene:
             skip = np.zeros(K, bool)
             skip[ee] = par(X0[ee]) & par(X1[ee])
             roots[skip] = np.nan
+        # activation margin: dhat for pairs approaching from outside the barrier
+        # zone, half the current distance for pairs already inside it (reading)
+        q_start, _ = classify(pairs.kind, X0)
+        d_start = np.sqrt(q_start)
+        margin = np.where(d_start < self.dhat, 0.5 * d_start, self.dhat)
         done = np.zeros(K, dtype=bool)
         t_prev = np.zeros(K)
         for k in range(3):
@@ -763,7 +778,7 @@ class OracleScene:
             tk = np.clip(r[idx], 0.0, 1.0)
             Xk = X0[idx] + tk[:, None, None] * P[idx]
             q, case = classify(pairs.kind[idx], Xk)
-            act = np.sqrt(q) < CCD_EPS + self.dhat
+            act = np.sqrt(q) < CCD_EPS + margin[idx]
             ai = idx[act]
             tau_a = tk[act]
             case_a = case[act]
@@ -865,8 +880,12 @@ class OracleScene:
             self._log(f"iteration {it}: direct solve done", t0)
             P = np.zeros_like(x)
             P[self.free_idx] = dx.reshape(-1, 3)
-            swept = self.candidate_pairs(x, disp=P)
-            amax = self.ccd(x, P, swept)
+            sw = 1.0
+            pmax = float(np.sqrt((P * P).sum(1).max())) if len(P) else 0.0
+            while sw * pmax > self.sweep_len and sw > 1e-30:
+                sw *= 0.5
+            swept = self.candidate_pairs(x, disp=sw * P)
+            amax = sw * self.ccd(x, sw * P, swept)
             self._log(f"iteration {it}: CCD over {len(swept)} pairs, alpha_max = {amax:.3e}", t0)
             alpha = amax
             while True:

@@ -106,6 +106,30 @@ __global__ void k_aug_carry(int nnew, const uint64_t *nkey, const uint64_t *okey
   ns[j] = k >= 0 ? os[k] : 0.0;
 }
 
+// -|p_i|^2 per vertex (for the largest displacement of a step)
+__global__ void k_neg_norm2(const double *__restrict__ p, double *__restrict__ out, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = -(p[3 * i] * p[3 * i] + p[3 * i + 1] * p[3 * i + 1] + p[3 * i + 2] * p[3 * i + 2]);
+}
+
+__global__ void k_scale(const double *__restrict__ a, double f, double *__restrict__ b, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = f * a[i];
+}
+
+// Largest sweep s (a power of 1/2, at most 1) for which no vertex moves more
+// than kSweepCells hash cells along s p: the swept candidate boxes then stay
+// on the hash's cell path (memory-limited halving of the step, Sec. 5.2).
+constexpr double kSweepCells = 16.0;
+static double sweep_limit(Scene &s, const double *p) {
+  if (s.tau.grow((size_t)(s.N + 1) * 8)) return 1.0;
+  hipLaunchKernelGGL(k_neg_norm2, dim3(blocks_for(s.N, 256)), dim3(256), 0, s.stream, p, s.tau.as<double>(), s.N);
+  double pmax = std::sqrt(std::max(0.0, -reduce_min(s, s.tau.as<double>(), s.N)));
+  double sw = 1.0;
+  while (sw * pmax > kSweepCells * s.cell && sw > 1e-30) sw *= 0.5;
+  return sw;
+}
+
 __global__ void k_neg(const double *a, double *b, int n) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) b[i] = -a[i];
@@ -408,10 +432,28 @@ static int newton_solve(Scene &s, bal_step_stats *st, bool record) {
     int retries = 0;
     for (;;) {
       auto tcc = clk::now();
-      if ((rc = build_candidates(s, s.cand2, x, dx))) return rc;
+      // swept candidates over [x, x + sw dx]: sw halves while the sweep is too
+      // long for the hash or the pass exceeds its work bound
+      double sw = sweep_limit(s, dx);
+      const double *pp = dx;
+      for (;;) {
+        if (sw < 1.0) {
+          if (s.psweep.grow(3 * (size_t)s.N * 8)) return BAL_E_OOM;
+          hipLaunchKernelGGL(k_scale, dim3(blocks_for(3 * s.N, 256)), dim3(256), 0, s.stream, dx, sw,
+                             s.psweep.as<double>(), 3 * s.N);
+          pp = s.psweep.as<double>();
+        }
+        rc = build_candidates(s, s.cand2, x, pp);
+        if (rc == BAL_E_CAPACITY && sw > 1e-30) {
+          sw *= 0.5;
+          continue;
+        }
+        if (rc) return rc;
+        break;
+      }
       if (s.tau.grow((size_t)(s.cand2.n + 1) * 8)) return BAL_E_OOM;
-      launch_ccd(s, s.cand2, x, dx, s.tau.as<double>());
-      amax = std::min(1.0, s.cand2.n ? reduce_min(s, s.tau.as<double>(), s.cand2.n) : 1.0);
+      launch_ccd(s, s.cand2, x, pp, s.tau.as<double>());
+      amax = sw * std::min(1.0, s.cand2.n ? reduce_min(s, s.tau.as<double>(), s.cand2.n) : 1.0);
       S.sec_ccd += since(tcc);
       auto tl = clk::now();
       int valid, nact;
@@ -866,7 +908,7 @@ void bal_destroy_scene(bal_scene *h) {
                   &s.h_cnt, &s.h_off, &s.h_key, &s.h_prim, &s.h_bcnt, &s.h_bstart, &s.h_bfill, &s.h_skey,
                   &s.h_sprim, &s.h_large, &s.h_nlarge, &s.h_qcnt, &s.h_qoff, &s.h_out, &s.qoff_pt, &s.out_pt,
                   &s.qoff_ee, &s.out_ee, &s.r, &s.z, &s.pv, &s.pv2, &s.q, &s.pcg_ctl, &s.warm_ctl, &s.partial, &s.counter,
-                  &s.scan_tmp, &s.red_out, &s.flags, &s.node_e, &s.cand_e, &s.mask, &s.mask_off, &s.tau, &s.rhs};
+                  &s.scan_tmp, &s.red_out, &s.flags, &s.node_e, &s.cand_e, &s.mask, &s.mask_off, &s.tau, &s.rhs, &s.psweep};
   for (DBuf *b : bufs) b->release();
   PairList *pls[] = {&s.cand, &s.cand2, &s.uni, &s.augtmp};
   for (PairList *pl : pls) {

@@ -76,7 +76,7 @@ struct Scene {
       h_large, h_nlarge, h_qcnt, h_qoff, h_out, qoff_pt, out_pt, qoff_ee, out_ee;
   // PCG
   DBuf r, z, pv, pv2, q, pcg_ctl, warm_ctl, partial, counter, scan_tmp, red_out, flags;
-  DBuf node_e, cand_e, mask, mask_off, tau, rhs;
+  DBuf node_e, cand_e, mask, mask_off, tau, rhs, psweep;
   DBuf pin;     // pinned host scratch (hipHostMalloc)
   // graph replay of PCG chunks (re-captured when a buffer moves)
   bool use_graphs = true;

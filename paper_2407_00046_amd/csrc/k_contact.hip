@@ -382,6 +382,12 @@ __global__ void k_ccd(int n, const int *__restrict__ kind, const int4 *__restric
   double c3 = dot(u1, cross(v1, w1));
   double roots[3];
   int nr = cubic_roots(c3, c2, c1, c0, -kCcdEps, 1.0 + kCcdEps, roots);
+  // activation margin: dhat for a pair approaching from outside the barrier
+  // zone; half the current distance for a pair already inside it (a margin of
+  // dhat there would stop every near miss of two primitives sliding in contact)
+  int cs0;
+  const double d0 = sqrt(pair_classify(kd, X0, &cs0));
+  const double margin = d0 < dhat ? 0.5 * d0 : dhat;
   double tprev = 0.0;
   for (int k = 0; k < nr; ++k) {
     if (roots[k] <= kCcdEps) continue;  // coplanar at the (feasible) start of the step
@@ -391,7 +397,7 @@ __global__ void k_ccd(int n, const int *__restrict__ kind, const int4 *__restric
     for (int m = 0; m < 4; ++m) Xt[m] = X0[m] + tk * P[m];
     int cs;
     double dt = sqrt(pair_classify(kd, Xt, &cs));
-    if (dt < kCcdEps + dhat) {
+    if (dt < kCcdEps + margin) {
       double t = tk;
       if (cs == 0 || cs == 7) {
         for (int it = 0; it < 400; ++it) {

@@ -20,6 +20,10 @@ constexpr int kHB = 256;
 constexpr long kLargeCells = 64;
 constexpr long kQueryCells = 4096;
 constexpr int kOff = 1 << 20;
+// Bound on the box tests of one pass (direct tests of large entries and of
+// large queries); beyond it the pass reports BAL_E_CAPACITY and the caller
+// shortens the sweep.
+constexpr double kWorkCap = (double)(1 << 28);
 
 struct Box { double lo[3], hi[3]; };
 
@@ -228,6 +232,14 @@ __global__ void k_query_write(QueryArgs A, const int *qoff, int *outb) {
   }
 }
 
+// Queries whose box is tested directly against every entry.
+__global__ void k_big_queries(QueryArgs A, int *nbig) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= A.nq) return;
+  Box qb = prim_box(A.qtype, q, A.sv, A.st, A.se, A.x, A.p, 0.0);
+  if ((A.qtype == 2 && A.qlarge[q]) || box_cells(qb.lo, qb.hi, A.ih) > (double)kQueryCells) atomicAdd(nbig, 1);
+}
+
 __global__ void k_large_flag(int n, const Box *ebox, double ih, uint8_t *fl) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -313,6 +325,13 @@ static int hash_half(Scene &s, int qtype, int etype, const double *x, const doub
   A.fr = s.freev.as<uint8_t>(); A.nbody = s.nb; A.x = x; A.p = p; A.ebox = ebox; A.ih = ih; A.mask = M - 1;
   A.bstart = s.h_bstart.as<int>(); A.skey = s.h_skey.as<uint64_t>(); A.sprim = s.h_sprim.as<int>();
   A.large_list = s.h_large.as<int>(); A.nlarge = nlarge; A.qlarge = qlarge;
+  if (nq > 0) {
+    hipMemsetAsync(nlarge_d + 1, 0, sizeof(int), s.stream);
+    hipLaunchKernelGGL(k_big_queries, dim3(blocks_for(nq, 128)), dim3(128), 0, s.stream, A, nlarge_d + 1);
+    hipMemcpyAsync(hn, nlarge_d + 1, sizeof(int), hipMemcpyDeviceToHost, s.stream);
+    hipStreamSynchronize(s.stream);
+    if ((double)nq * nlarge + (double)hn[0] * ne > kWorkCap) return BAL_E_CAPACITY;
+  }
   if (s.h_qcnt.grow((size_t)(nq + 1) * sizeof(int)) || qoff_buf.grow((size_t)(nq + 1) * sizeof(int))) return BAL_E_OOM;
   hipMemsetAsync(s.h_qcnt.p, 0, (nq + 1) * sizeof(int), s.stream);
   if (nq > 0) hipLaunchKernelGGL(k_query_count, dim3(blocks_for(nq, 128)), dim3(128), 0, s.stream, A, s.h_qcnt.as<int>());
