@@ -78,6 +78,9 @@ typedef struct bal_scene_desc {
   double dhat;                 /* barrier offset dhat (eq. IPC-barrier) */
   double newton_rtol;          /* ||e^l|| <= rtol ||e^0|| (Alg. 1), default 1e-4 */
   double pcg_rtol;             /* ||r^k|| <= rtol ||r^0|| (App. B), default 1e-4 */
+  double sigma_fixed;          /* 0: adaptive barrier stiffness (sigma^0 and growth rule, Sec. 3.4);
+                                  > 0: sigma held at this value in every step, so that a step is
+                                  the minimiser of one smooth energy (differentiable rollouts) */
   int32_t max_newton;          /* default 1000 */
   int32_t max_pcg;             /* PCG iteration cap per Newton iteration, default 20000 */
   int32_t pcg_stall_window;    /* stop PCG when no new minimum of ||r|| in this many

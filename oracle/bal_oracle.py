@@ -278,6 +278,7 @@ class Params:
     min_alpha: float = 1e-9       # line-search floor (App. B)
     pair_mode: str = "brute"      # "brute" or "kdtree" (superset for large scenes)
     verbose: bool = False         # print one line per phase of each Newton iteration
+    sigma_fixed: float = 0.0      # > 0: sigma held at this value (no sigma^0, no growth)
 
 
 class OracleScene:
@@ -836,6 +837,8 @@ class OracleScene:
         y = self.predictor(x_t, v_t)
         x = x_t.copy()
         st = ALState()
+        if p.sigma_fixed > 0.0:
+            st.sigma = st.sigma0 = float(p.sigma_fixed)
         prev_min = np.inf
         e0 = None
         converged = False
@@ -918,7 +921,7 @@ class OracleScene:
                 da, _ = self.distances(xn, st.aug)
                 st.s = np.maximum(-st.mu / st.sigma - dh + da, 0.0)
                 st.mu = st.mu + st.sigma * barrier_np(da, dh + st.s)
-            if dn.size and dn.min() < 1e-2 * dh and st.sigma is not None:
+            if dn.size and dn.min() < 1e-2 * dh and st.sigma is not None and not p.sigma_fixed > 0.0:
                 st.sigma = max(1.2 * st.sigma, 100.0 * st.sigma0)
             x = xn
         self.x = x

@@ -37,7 +37,7 @@ class bal_scene_desc(C.Structure):
         ("n_obs_verts", C.c_int32), ("n_obs_tris", C.c_int32),
         ("obs_pos", _dp), ("obs_tris", _ip), ("x0", _dp), ("v0", _dp),
         ("dt", C.c_double), ("gravity", C.c_double * 3), ("dhat", C.c_double),
-        ("newton_rtol", C.c_double), ("pcg_rtol", C.c_double),
+        ("newton_rtol", C.c_double), ("pcg_rtol", C.c_double), ("sigma_fixed", C.c_double),
         ("max_newton", C.c_int32), ("max_pcg", C.c_int32), ("pcg_stall_window", C.c_int32),
         ("max_contacts", C.c_int32), ("warm_iters", C.c_int32), ("precision", C.c_int32),
         ("warm_start", C.c_int32), ("use_al", C.c_int32), ("device", C.c_int32), ("stream", C.c_void_p),

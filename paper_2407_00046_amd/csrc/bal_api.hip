@@ -366,9 +366,9 @@ static int newton_solve(Scene &s, bal_step_stats *st, bool record) {
   copy3(s, s.v_t.as<double>(), s.v.as<double>());
   launch_predictor(s);
   s.n_aug = 0;
-  s.sigma_set = false;
-  s.sigma = 0.0;
-  s.sigma0 = 0.0;
+  // a fixed barrier stiffness replaces sigma^0 and the growth rule
+  s.sigma_set = d.sigma_fixed > 0.0;
+  s.sigma = s.sigma0 = d.sigma_fixed > 0.0 ? d.sigma_fixed : 0.0;
   if (record) s.trace.clear();
   bal_step_stats S{};
   s.spmv_ms = 0.0;
@@ -507,7 +507,8 @@ static int newton_solve(Scene &s, bal_step_stats *st, bool record) {
     if (s.n_aug) launch_aug_update(s, xtr);
     launch_pair_distance(s, s.cand2, xtr, s.cand2.d.as<double>(), s.cand2.cs.as<int>());
     double dmin_new = min_or(s, s.cand2, INFINITY);
-    if (dmin_new < 1e-2 * dh && s.sigma_set) s.sigma = std::max(1.2 * s.sigma, 100.0 * s.sigma0);
+    if (dmin_new < 1e-2 * dh && s.sigma_set && !(d.sigma_fixed > 0.0))
+      s.sigma = std::max(1.2 * s.sigma, 100.0 * s.sigma0);
     copy3(s, x, xtr);
     std::swap(s.cand, s.cand2);
   }
@@ -826,6 +827,7 @@ static int validate_desc(const bal_scene_desc *d) {
   if (d->n_obs_verts < 0 || d->n_obs_tris < 0 || (d->n_obs_verts && !d->obs_pos) || (d->n_obs_tris && !d->obs_tris))
     return BAL_E_INVALID_ARG;
   if (!(d->dt > 0.0) || !(d->dhat > 0.0) || !std::isfinite(d->dt) || !std::isfinite(d->dhat)) return BAL_E_INVALID_ARG;
+  if (!(d->sigma_fixed >= 0.0) || !std::isfinite(d->sigma_fixed)) return BAL_E_INVALID_ARG;
   if (!finite_all(d->rest_pos, 3 * (size_t)d->n_verts) || !finite_all(d->gravity, 3)) return BAL_E_INVALID_ARG;
   if (d->n_tets && (!finite_all(d->youngs, d->n_tets) || !finite_all(d->poisson, d->n_tets) ||
                     !finite_all(d->density, d->n_tets)))
@@ -1266,18 +1268,29 @@ int bal_step_adjoint(bal_scene *h, const double *x_t, const double *v_t, const d
   double sig = s.sigma_set ? s.sigma : 0.0;
   if ((rc = linearize_at(s, x, 0, sig))) return rc;
   double bn = std::sqrt(dot_free(s, s.rhs.as<double>(), s.rhs.as<double>()));
-  double save = s.desc.pcg_rtol;
+  // the adjoint system is solved to 1e-10 without the stagnation exit (an
+  // early stop here is an error in the gradient, not a cheaper Newton step)
+  const double save = s.desc.pcg_rtol;
+  const int save_stall = s.desc.pcg_stall_window;
+  const int cap = std::max(s.desc.max_pcg, 200000);
   s.desc.pcg_rtol = 1e-10;
+  s.desc.pcg_stall_window = 0;
   int it = 0;
   double rel = 0.0;
   double *lam = s.dx.as<double>();
-  rc = pcg_solve(s, s.rhs.as<double>(), lam, bn, s.desc.max_pcg, 0, 0, &it, &rel);
+  rc = pcg_solve(s, s.rhs.as<double>(), lam, bn, cap, 0, 0, &it, &rel);
   if (rc == BAL_E_NO_CONVERGENCE) {
     // negative curvature: fall back to the projected Hessian
-    if ((rc = linearize_at(s, x, 1, sig))) { s.desc.pcg_rtol = save; return rc; }
-    rc = pcg_solve(s, s.rhs.as<double>(), lam, bn, s.desc.max_pcg, 0, 0, &it, &rel);
+    if ((rc = linearize_at(s, x, 1, sig))) {
+      s.desc.pcg_rtol = save;
+      s.desc.pcg_stall_window = save_stall;
+      return rc;
+    }
+    rc = pcg_solve(s, s.rhs.as<double>(), lam, bn, cap, 0, 0, &it, &rel);
   }
   s.desc.pcg_rtol = save;
+  s.desc.pcg_stall_window = save_stall;
+  if (rc == BAL_OK && rel > 1e-10) rc = BAL_E_NO_CONVERGENCE;
   if (rc != BAL_OK && rc != BAL_E_NO_CONVERGENCE) return rc;
   // tet_g holds grad Psi_e at x_{t+1} from the linearization
   DBuf gEd, gxo, gvo, Ed;

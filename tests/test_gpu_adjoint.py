@@ -85,3 +85,70 @@ def test_rollout_gradient_matches_central_differences():
     print(f"E: adjoint {an_E:.8e} fd {float(fd_E):.8e}; v0: adjoint {an_v:.8e} fd {float(fd_v):.8e}")
     assert abs(an_E - float(fd_E)) <= 1e-4 * abs(float(fd_E))
     assert abs(an_v - float(fd_v)) <= 1e-4 * abs(float(fd_v))
+
+
+@pytest.mark.parametrize("box", [True, False])
+def test_beam_full_size_rollout_gradients(box):
+    """The full beam (128x16x16 cells, 163,840 tets, clamped), with and without
+    the box it falls onto, sigma fixed at 1e3 and no A' (with the adaptive
+    sigma^0 and growth rule the step map depends on the state discretely and
+    is not differentiable): 20 steps with checkpoints every 5.  Loss = squared
+    distance of the free-end centroid to a target 1 cm below its position in a
+    rollout with uniform E = 1e6 (the offset keeps the loss's first-order
+    change well above the rollouts' convergence noise).  Gradients wrt log E
+    (random direction of unit RMS per element) and v0 (random direction) from
+    BalRollout against Richardson-extrapolated central differences.  With the
+    box, the central differences of the v0 direction scatter by a few percent
+    between step sizes (the steps' convergence floor meets the contact), so
+    that comparison is held to 5e-2; without it, to 1e-4 like the rest."""
+    import torch
+    from paper_2407_00046_amd import Scene
+    from paper_2407_00046_amd.bal import BalRollout
+    sc = scenes.beam()
+    if not box:
+        sc["obs_pos"] = np.zeros((0, 3))
+        sc["obs_tris"] = np.zeros((0, 3), np.int32)
+    T, every = 20, 5
+    # a differentiable step map: fixed barrier stiffness and no augmentation set
+    g = Scene(sc, newton_rtol=1e-9, pcg_rtol=1e-12, max_newton=300, use_al=False, sigma_fixed=1e3)
+    pos = sc["rest_pos"]
+    tip = np.nonzero(np.abs(pos[:, 0] - pos[:, 0].max()) < 1e-9)[0]
+    ref = BalRollout.apply(torch.full((len(sc["youngs"]),), 1e6, dtype=torch.float64),
+                           torch.tensor(sc["v0"]), g, sc["x0"], T, every)
+    target = ref[tip].mean(0).detach() + torch.tensor([0.0, -0.01, 0.0], dtype=torch.float64)
+    E0 = torch.tensor(sc["youngs"], dtype=torch.float64, requires_grad=True)
+    v0 = torch.tensor(sc["v0"], dtype=torch.float64, requires_grad=True)
+
+    def loss_of(E, v):
+        xT = BalRollout.apply(E, v, g, sc["x0"], T, every)
+        return ((xT[tip].mean(0) - target) ** 2).sum()
+
+    L = loss_of(E0, v0)
+    L.backward()
+    rng = np.random.default_rng(1)
+    dlogE = torch.tensor(rng.normal(size=len(sc["youngs"])))
+    dlogE /= torch.sqrt((dlogE ** 2).mean())
+    # a random uniform velocity (0.1 m/s) plus random per-vertex noise: per-vertex
+    # noise alone averages out at the free end, below the rollouts' noise floor
+    dv = torch.zeros_like(v0)
+    free = torch.tensor(sc["fixed"] == 0)
+    c = rng.normal(size=3)
+    dv[free] = torch.tensor(0.1 * c / np.linalg.norm(c) + 0.01 * rng.normal(size=(int(free.sum()), 3)))
+    with torch.no_grad():
+        an_E = float((E0.grad * E0 * dlogE).sum())
+        an_v = float((v0.grad * dv).sum())
+
+        def richardson(f, eps):
+            """Central differences at eps and eps/2 with the O(eps^2) term removed:
+            the steps' convergence floor (gradient residual ~1e-7 in FP64) puts
+            noise of order 1e-9 m on the free end, so eps cannot be small."""
+            d1 = (f(eps) - f(-eps)) / (2 * eps)
+            d2 = (f(0.5 * eps) - f(-0.5 * eps)) / eps
+            return d1, d2, (4.0 * d2 - d1) / 3.0
+
+        e1, e2, fd_E = richardson(lambda e: float(loss_of(E0 * torch.exp(e * dlogE), v0)), 1e-2)
+        v1, v2, fd_v = richardson(lambda e: float(loss_of(E0, v0 + e * dv)), 1e-2)
+    print(f"loss {float(L):.6e}; E: adjoint {an_E:.8e} fd {e1:.8e} {e2:.8e} -> {fd_E:.8e}; "
+          f"v0: adjoint {an_v:.8e} fd {v1:.8e} {v2:.8e} -> {fd_v:.8e}")
+    assert abs(an_E - fd_E) <= 1e-4 * abs(fd_E)
+    assert abs(an_v - fd_v) <= (5e-2 if box else 1e-4) * abs(fd_v)

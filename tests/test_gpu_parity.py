@@ -165,7 +165,8 @@ def test_ccd_bound(contact_case):
 
 def run_both(sc, n_steps, precision="fp64", newton_rtol=1e-7, pcg_rtol=1e-12, **kw):
     g = lib_scene(sc, precision=precision, newton_rtol=newton_rtol, pcg_rtol=pcg_rtol, max_newton=200, **kw)
-    o = OracleScene(sc, Params(newton_rtol=newton_rtol, max_newton=200))
+    o = OracleScene(sc, Params(newton_rtol=newton_rtol, max_newton=200, use_al=kw.get("use_al", True),
+                               sigma_fixed=kw.get("sigma_fixed", 0.0)))
     n = sc["rest_pos"].shape[0]
     L = np.linalg.norm(sc["x0"].max(0) - sc["x0"].min(0))
     errs = []
@@ -185,6 +186,12 @@ def run_both(sc, n_steps, precision="fp64", newton_rtol=1e-7, pcg_rtol=1e-12, **
 
 def test_tiny_cube_steps_fp64():
     errs = run_both(scenes.tiny_cube(), 3)
+    assert max(errs) <= 1e-6
+
+
+def test_tiny_cube_steps_fixed_sigma_plain_barrier():
+    """The differentiable-rollout configuration: sigma held fixed, no A'."""
+    errs = run_both(scenes.tiny_cube(), 3, use_al=False, sigma_fixed=1e3)
     assert max(errs) <= 1e-6
 
 
