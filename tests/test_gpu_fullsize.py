@@ -119,3 +119,32 @@ def test_spmv_grid_128_sampled_rows(prec):
 
 def test_chain_net_large_sampled_rows():
     compare_sampled(scenes.chain_net_large(), "mixed", perturb=1e-5)
+
+
+def test_chain_net_step_properties():
+    """One mixed-precision step of the chain net (401,280 tets, E = 1e9 links)
+    with a 2000-iteration PCG stagnation window (the paper's 100 stops these
+    stiff solves far from their tolerance): the Newton test passes, no tet
+    inverts, every surface pair keeps d > 0 (the oracle's distances at the end
+    state, on its own candidate pairs) and the fixed rings stay put."""
+    from paper_2407_00046_amd import Scene
+    sc = scenes.chain_net()
+    g = Scene(sc, precision="mixed", newton_rtol=1e-4, pcg_rtol=1e-4, max_newton=400, pcg_stall_window=2000,
+              device=0)
+    st = g.step(allow=(0, -7))
+    x1, v1 = g.get_state()
+    g.close()
+    print(f"chain net step: status {st['status']}, {st['newton_iters']} Newton, {st['pcg_iters']} PCG iterations, "
+          f"{st['n_active_max']} active pairs, {st['sec_total']:.1f} s")
+    assert st["converged"] == 1
+    o = OracleScene(sc, Params(pair_mode="kdtree"))
+    x = np.concatenate([x1, np.asarray(sc["obs_pos"]).reshape(-1, 3)])
+    pos, tets = x, sc["tets"].astype(np.int64)
+    e = pos[tets[:, 1:]] - pos[tets[:, :1]]
+    assert np.einsum("ij,ij->i", e[:, 0], np.cross(e[:, 1], e[:, 2])).min() > 0.0
+    pairs = o.candidate_pairs(x)
+    d, _ = o.distances(x, pairs)
+    assert d.min() > 0.0
+    # fixed rings stay put
+    fx = sc["fixed"] == 1
+    assert np.array_equal(x1[fx], sc["x0"][fx]) and np.all(v1[fx] == 0.0)
