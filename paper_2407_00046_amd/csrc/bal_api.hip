@@ -875,6 +875,87 @@ void bal_desc_defaults(bal_scene_desc *d) {
   d->use_al = 1;
 }
 
+// ---- the caller's vertex order at the boundary
+__global__ void k_gather_body3(int nb, const int *__restrict__ perm, const double *__restrict__ ext,
+                               double *__restrict__ in) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nb) return;
+  const int o = perm[i];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) in[3 * i + c] = ext[3 * o + c];
+}
+__global__ void k_scatter_body3(int nb, const int *__restrict__ perm, const double *__restrict__ in,
+                                double *__restrict__ ext) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nb) return;
+  const int o = perm[i];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) ext[3 * o + c] = in[3 * i + c];
+}
+
+// The caller's [rows][3] array (rows = n_verts: body; rows = N: body then
+// obstacles), host or device, into the internal order at dst (device).
+static int import3(Scene &s, const double *ext, double *dst, int rows, bool on_device) {
+  const size_t bytes = 3 * (size_t)rows * 8;
+  if (hipMemcpyAsync(s.stage.p, ext, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                     s.stream) != hipSuccess)
+    return BAL_E_HIP;
+  hipLaunchKernelGGL(k_gather_body3, dim3(blocks_for(s.nb, 256)), dim3(256), 0, s.stream, s.nb, s.perm_d.as<int>(),
+                     s.stage.as<double>(), dst);
+  if (rows > s.nb)
+    hipMemcpyAsync(dst + 3 * (size_t)s.nb, s.stage.as<double>() + 3 * (size_t)s.nb, 3 * (size_t)(rows - s.nb) * 8,
+                   hipMemcpyDeviceToDevice, s.stream);
+  return BAL_OK;
+}
+// Internal device array src to the caller's order at ext (host or device);
+// a host destination is complete after the stream is synchronised.
+static int export3(Scene &s, const double *src, double *ext, int rows, bool on_device) {
+  const size_t bytes = 3 * (size_t)rows * 8;
+  hipLaunchKernelGGL(k_scatter_body3, dim3(blocks_for(s.nb, 256)), dim3(256), 0, s.stream, s.nb, s.perm_d.as<int>(),
+                     src, s.stage.as<double>());
+  if (rows > s.nb)
+    hipMemcpyAsync(s.stage.as<double>() + 3 * (size_t)s.nb, src + 3 * (size_t)s.nb, 3 * (size_t)(rows - s.nb) * 8,
+                   hipMemcpyDeviceToDevice, s.stream);
+  return hip_ok(hipMemcpyAsync(ext, s.stage.p, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                               s.stream));
+}
+static inline int ext_vertex(const Scene &s, int v) { return v < s.nb ? s.perm_h[v] : v; }
+
+// Morton order (10 bits per axis over the bounding box) of the body's rest
+// positions: vertices close in space get close indices, so the rows that share
+// matrix blocks and vector entries are processed close together and their
+// second uses meet in cache.  Returns internal -> caller index.
+static std::vector<int> morton_order(const double *X, int n) {
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int i = 0; i < n; ++i)
+    for (int c = 0; c < 3; ++c) {
+      lo[c] = std::min(lo[c], X[3 * i + c]);
+      hi[c] = std::max(hi[c], X[3 * i + c]);
+    }
+  auto spread = [](uint64_t v) {  // 10 bits to every third bit
+    v &= 0x3ff;
+    v = (v | (v << 16)) & 0x30000ffULL;
+    v = (v | (v << 8)) & 0x300f00fULL;
+    v = (v | (v << 4)) & 0x30c30c3ULL;
+    v = (v | (v << 2)) & 0x9249249ULL;
+    return v;
+  };
+  std::vector<std::pair<uint64_t, int>> key(n);
+  for (int i = 0; i < n; ++i) {
+    uint64_t q[3];
+    for (int c = 0; c < 3; ++c) {
+      double ext = hi[c] - lo[c];
+      double f = ext > 0.0 ? (X[3 * i + c] - lo[c]) / ext : 0.0;
+      q[c] = (uint64_t)std::min(1023.0, std::max(0.0, std::floor(f * 1024.0)));
+    }
+    key[i] = {spread(q[0]) | (spread(q[1]) << 1) | (spread(q[2]) << 2), i};
+  }
+  std::sort(key.begin(), key.end());
+  std::vector<int> perm(n);
+  for (int i = 0; i < n; ++i) perm[i] = key[i].second;
+  return perm;
+}
+
 int bal_create_scene(const bal_scene_desc *desc, bal_scene **out) {
   if (!out) return BAL_E_INVALID_ARG;
   *out = nullptr;
@@ -883,7 +964,40 @@ int bal_create_scene(const bal_scene_desc *desc, bal_scene **out) {
   bal_scene *h = new (std::nothrow) bal_scene();
   if (!h) return BAL_E_OOM;
   try {
-    rc = build_scene(h->s, desc);
+    // the caller's arrays in the internal vertex order
+    const int nb = desc->n_verts, T = desc->n_tets;
+    std::vector<int> perm = morton_order(desc->rest_pos, nb), inv(nb);
+    for (int i = 0; i < nb; ++i) inv[perm[i]] = i;
+    std::vector<double> X(3 * (size_t)nb), x0, v0;
+    std::vector<uint8_t> fx;
+    std::vector<int32_t> tets(4 * (size_t)T);
+    for (int i = 0; i < nb; ++i)
+      for (int c = 0; c < 3; ++c) X[3 * i + c] = desc->rest_pos[3 * perm[i] + c];
+    for (size_t k = 0; k < tets.size(); ++k) tets[k] = inv[desc->tets[k]];
+    bal_scene_desc d = *desc;
+    d.rest_pos = X.data();
+    d.tets = tets.data();
+    if (desc->x0) {
+      x0.resize(3 * (size_t)nb);
+      for (int i = 0; i < nb; ++i)
+        for (int c = 0; c < 3; ++c) x0[3 * i + c] = desc->x0[3 * perm[i] + c];
+      d.x0 = x0.data();
+    }
+    if (desc->v0) {
+      v0.resize(3 * (size_t)nb);
+      for (int i = 0; i < nb; ++i)
+        for (int c = 0; c < 3; ++c) v0[3 * i + c] = desc->v0[3 * perm[i] + c];
+      d.v0 = v0.data();
+    }
+    if (desc->fixed) {
+      fx.resize(nb);
+      for (int i = 0; i < nb; ++i) fx[i] = desc->fixed[perm[i]];
+      d.fixed = fx.data();
+    }
+    h->s.perm_h = perm;
+    rc = build_scene(h->s, &d);
+    if (!rc) rc = upload(h->s, h->s.perm_d, perm.data(), std::max(nb, 1));
+    if (!rc && h->s.stage.grow(3 * (size_t)h->s.N * 8 + 8)) rc = BAL_E_OOM;
   } catch (...) {
     rc = BAL_E_OOM;
   }
@@ -901,7 +1015,7 @@ void bal_destroy_scene(bal_scene *h) {
   hipSetDevice(s.dev);
   hipStreamSynchronize(s.stream);
   DBuf *bufs[] = {&s.tets, &s.tc, &s.mass, &s.freev, &s.node_tet_ptr, &s.node_tet_src, &s.row_ptr, &s.col_idx,
-                  &s.blk_src_ptr, &s.blk_src, &s.up_ptr, &s.up_ent, &s.sv, &s.st, &s.se, &s.x, &s.v, &s.x_t, &s.v_t, &s.y,
+                  &s.blk_src_ptr, &s.blk_src, &s.up_ptr, &s.up_ent, &s.perm_d, &s.stage, &s.sv, &s.st, &s.se, &s.x, &s.v, &s.x_t, &s.v_t, &s.y,
                   &s.xtrial, &s.dx, &s.tet_e, &s.tet_g, &s.tet_tr, &s.tet_blk, &s.val, &s.Dblk, &s.Dinv, &s.e_nodes,
                   &s.group, &s.grad, &s.grad_b, &s.uni_flag, &s.uni_aug, &s.pair_e, &s.pair_g, &s.pair_tr,
                   &s.pair_blk, &s.cdiag_ptr, &s.cdiag_src, &s.coff_ptr, &s.coff_col, &s.coff_src, &s.ccount,
@@ -954,10 +1068,10 @@ int bal_get_state(const bal_scene *h, double *x_out, double *v_out, int on_devic
   if (!h) return BAL_E_INVALID_ARG;
   const Scene &s = h->s;
   hipSetDevice(s.dev);
-  hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
-  size_t bytes = (size_t)3 * s.nb * 8;
-  if (x_out && hipMemcpyAsync(x_out, s.x.p, bytes, k, s.stream) != hipSuccess) return BAL_E_HIP;
-  if (v_out && hipMemcpyAsync(v_out, s.v.p, bytes, k, s.stream) != hipSuccess) return BAL_E_HIP;
+  Scene &sm = const_cast<Scene &>(s);  // the staging buffer is scratch
+  int rc;
+  if (x_out && (rc = export3(sm, s.x.as<double>(), x_out, s.nb, on_device != 0))) return rc;
+  if (v_out && (rc = export3(sm, s.v.as<double>(), v_out, s.nb, on_device != 0))) return rc;
   return hip_ok(hipStreamSynchronize(s.stream));
 }
 
@@ -969,10 +1083,11 @@ int bal_set_state(bal_scene *h, const double *x, const double *v, int on_device)
   if (!on_device) {
     if ((x && !finite_all(x, 3 * (size_t)s.nb)) || (v && !finite_all(v, 3 * (size_t)s.nb))) return BAL_E_INVALID_ARG;
   }
-  hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-  if (x && hipMemcpyAsync(s.x.p, x, bytes, k, s.stream) != hipSuccess) return BAL_E_HIP;
+  (void)bytes;
+  int rc;
+  if (x && (rc = import3(s, x, s.x.as<double>(), s.nb, on_device != 0))) return rc;
   if (v) {
-    if (hipMemcpyAsync(s.v.p, v, bytes, k, s.stream) != hipSuccess) return BAL_E_HIP;
+    if ((rc = import3(s, v, s.v.as<double>(), s.nb, on_device != 0))) return rc;
     // fixed vertices keep zero velocity
     const std::vector<uint8_t> &fr = s.free_h;
     std::vector<double> vh(3 * (size_t)s.N);
@@ -1033,9 +1148,12 @@ int bal_get_surface(const bal_scene *h, int32_t *n_sv, int32_t *verts, int32_t *
   if (n_sv) *n_sv = s.nsv;
   if (n_st) *n_st = s.nst;
   if (n_se) *n_se = s.nse;
-  if (verts) std::copy(s.sv_h.begin(), s.sv_h.end(), verts);
-  if (tris) std::copy(s.st_h.begin(), s.st_h.end(), tris);
-  if (edges) std::copy(s.se_h.begin(), s.se_h.end(), edges);
+  if (verts)
+    for (size_t k = 0; k < s.sv_h.size(); ++k) verts[k] = ext_vertex(s, s.sv_h[k]);
+  if (tris)
+    for (size_t k = 0; k < s.st_h.size(); ++k) tris[k] = ext_vertex(s, s.st_h[k]);
+  if (edges)
+    for (size_t k = 0; k < s.se_h.size(); ++k) edges[k] = ext_vertex(s, s.se_h[k]);
   return BAL_OK;
 }
 
@@ -1050,8 +1168,9 @@ int bal_linearize(bal_scene *h, const double *x_all, const bal_al_state *al, int
   copy3(s, s.x_t.as<double>(), s.x.as<double>());
   copy3(s, s.v_t.as<double>(), s.v.as<double>());
   launch_predictor(s);
-  hipMemcpyAsync(s.xtrial.p, x_all, n3 * 8, hipMemcpyHostToDevice, s.stream);
   double *x = s.xtrial.as<double>();
+  int rcx = import3(s, x_all, x, s.N, false);
+  if (rcx) return rcx;
   // A' from the caller: nodes and canonical keys from the surface lists, sorted by key
   int na = al ? al->n_aug : 0;
   std::vector<int> idx(na);
@@ -1100,15 +1219,14 @@ int bal_linearize(bal_scene *h, const double *x_all, const bal_al_state *al, int
   if ((rc = energy_at(s, x, s.cand, sigma, &L, &valid, &nact))) return rc;
   if (energy) *energy = valid ? L : INFINITY;
   if (n_active) *n_active = nact;
-  if (grad_all) {
-    hipMemcpyAsync(grad_all, s.grad.p, n3 * 8, hipMemcpyDeviceToHost, s.stream);
-  }
+  if (grad_all && (rc = export3(s, s.grad.as<double>(), grad_all, s.N, false))) return rc;
   return sync(s);
 }
 
 static int upload_vec_precision(Scene &s, const double *host, void *dst) {
   size_t n3 = 3 * (size_t)s.N;
-  hipMemcpyAsync(s.rhs.p, host, n3 * 8, hipMemcpyHostToDevice, s.stream);
+  int rc = import3(s, host, s.rhs.as<double>(), s.N, false);
+  if (rc) return rc;
   if (s.mixed)
     hipLaunchKernelGGL(k_to_float, dim3(blocks_for(n3, 256)), dim3(256), 0, s.stream, s.rhs.as<double>(),
                        static_cast<float *>(dst), (int)n3);
@@ -1130,11 +1248,11 @@ int bal_hessian_apply(bal_scene *h, const double *v, double *out) {
                        s.rhs.as<double>(), (int)n3);
   else
     hipMemcpyAsync(s.rhs.p, s.q.p, n3 * 8, hipMemcpyDeviceToDevice, s.stream);
-  hipMemcpyAsync(out, s.rhs.p, n3 * 8, hipMemcpyDeviceToHost, s.stream);
-  int rc = sync(s);
+  int rc = export3(s, s.rhs.as<double>(), out, s.N, false);
+  if (!rc) rc = sync(s);
   for (int i = 0; i < s.N; ++i)
     if (!s.free_h[i])
-      for (int c = 0; c < 3; ++c) out[3 * i + c] = 0.0;
+      for (int c = 0; c < 3; ++c) out[3 * ext_vertex(s, i) + c] = 0.0;
   return rc;
 }
 
@@ -1143,9 +1261,16 @@ int bal_get_stiffness(const bal_scene *h, double *e_nodes, int32_t *groups) {
   const Scene &s = h->s;
   if (!s.linearized) return BAL_E_STATE;
   hipSetDevice(s.dev);
-  if (e_nodes) hipMemcpyAsync(e_nodes, s.e_nodes.p, (size_t)s.N * 8, hipMemcpyDeviceToHost, s.stream);
-  if (groups) hipMemcpyAsync(groups, s.group.p, (size_t)s.N * 4, hipMemcpyDeviceToHost, s.stream);
-  return hip_ok(hipStreamSynchronize(s.stream));
+  std::vector<double> e(s.N);
+  std::vector<int32_t> gr(s.N);
+  if (e_nodes) hipMemcpyAsync(e.data(), s.e_nodes.p, (size_t)s.N * 8, hipMemcpyDeviceToHost, s.stream);
+  if (groups) hipMemcpyAsync(gr.data(), s.group.p, (size_t)s.N * 4, hipMemcpyDeviceToHost, s.stream);
+  int rc = hip_ok(hipStreamSynchronize(s.stream));
+  for (int i = 0; i < s.N; ++i) {
+    if (e_nodes) e_nodes[ext_vertex(s, i)] = e[i];
+    if (groups) groups[ext_vertex(s, i)] = gr[i];
+  }
+  return rc;
 }
 
 int bal_solve(bal_scene *h, const double *rhs, double *z, int mode, double rtol, int32_t max_iters, int32_t *iters,
@@ -1155,10 +1280,9 @@ int bal_solve(bal_scene *h, const double *rhs, double *z, int mode, double rtol,
   if (!s.linearized) return BAL_E_STATE;
   hipSetDevice(s.dev);
   size_t n3 = 3 * (size_t)s.N;
-  std::vector<double> b(rhs, rhs + n3);
+  std::vector<double> b(n3);
   for (int i = 0; i < s.N; ++i)
-    if (!s.free_h[i])
-      for (int c = 0; c < 3; ++c) b[3 * i + c] = 0.0;
+    for (int c = 0; c < 3; ++c) b[3 * i + c] = s.free_h[i] ? rhs[3 * ext_vertex(s, i) + c] : 0.0;
   double bn = 0.0;
   for (double v : b) bn += v * v;
   bn = std::sqrt(bn);
@@ -1174,8 +1298,8 @@ int bal_solve(bal_scene *h, const double *rhs, double *z, int mode, double rtol,
   if (rc == BAL_OK && mode != 1) rc = pcg_solve(s, s.grad_b.as<double>(), xs, bn, max_iters, mode == 2, 0, &itg, &rel);
   s.desc.pcg_rtol = save;
   if (rc != BAL_OK && rc != BAL_E_NO_CONVERGENCE) return rc;
-  hipMemcpyAsync(z, xs, n3 * 8, hipMemcpyDeviceToHost, s.stream);
-  int rc2 = sync(s);
+  int rc2 = export3(s, xs, z, s.N, false);
+  if (!rc2) rc2 = sync(s);
   if (iters) *iters = mode == 1 ? itw : itg;
   if (rel_res) *rel_res = rel;
   return rc2 ? rc2 : rc;
@@ -1186,9 +1310,11 @@ int bal_ccd_bound(bal_scene *h, const double *x_all, const double *p_all, double
   Scene &s = h->s;
   hipSetDevice(s.dev);
   size_t n3 = 3 * (size_t)s.N;
-  hipMemcpyAsync(s.xtrial.p, x_all, n3 * 8, hipMemcpyHostToDevice, s.stream);
-  hipMemcpyAsync(s.rhs.p, p_all, n3 * 8, hipMemcpyHostToDevice, s.stream);
-  int rc = build_candidates(s, s.cand2, s.xtrial.as<double>(), s.rhs.as<double>());
+  (void)n3;
+  int rc;
+  if ((rc = import3(s, x_all, s.xtrial.as<double>(), s.N, false)) || (rc = import3(s, p_all, s.rhs.as<double>(), s.N, false)))
+    return rc;
+  rc = build_candidates(s, s.cand2, s.xtrial.as<double>(), s.rhs.as<double>());
   if (rc) return rc;
   if (s.tau.grow((size_t)(s.cand2.n + 1) * 8)) return BAL_E_OOM;
   launch_ccd(s, s.cand2, s.xtrial.as<double>(), s.rhs.as<double>(), s.tau.as<double>());
@@ -1202,9 +1328,11 @@ int bal_candidates(bal_scene *h, const double *x_all, const double *p_all, int32
   Scene &s = h->s;
   hipSetDevice(s.dev);
   size_t n3 = 3 * (size_t)s.N;
-  hipMemcpyAsync(s.xtrial.p, x_all, n3 * 8, hipMemcpyHostToDevice, s.stream);
-  if (p_all) hipMemcpyAsync(s.rhs.p, p_all, n3 * 8, hipMemcpyHostToDevice, s.stream);
-  int rc = build_candidates(s, s.cand2, s.xtrial.as<double>(), p_all ? s.rhs.as<double>() : nullptr);
+  (void)n3;
+  int rc;
+  if ((rc = import3(s, x_all, s.xtrial.as<double>(), s.N, false))) return rc;
+  if (p_all && (rc = import3(s, p_all, s.rhs.as<double>(), s.N, false))) return rc;
+  rc = build_candidates(s, s.cand2, s.xtrial.as<double>(), p_all ? s.rhs.as<double>() : nullptr);
   if (rc) return rc;
   launch_pair_distance(s, s.cand2, s.xtrial.as<double>(), s.cand2.d.as<double>(), s.cand2.cs.as<int>());
   int n = s.cand2.n;
@@ -1215,7 +1343,10 @@ int bal_candidates(bal_scene *h, const double *x_all, const double *p_all, int32
     if (nodes) hipMemcpyAsync(nodes, s.cand2.nodes.p, (size_t)m * 16, hipMemcpyDeviceToHost, s.stream);
     if (dist) hipMemcpyAsync(dist, s.cand2.d.p, (size_t)m * 8, hipMemcpyDeviceToHost, s.stream);
   }
-  return sync(s);
+  rc = sync(s);
+  if (nodes)
+    for (int k = 0; k < 4 * m; ++k) nodes[k] = ext_vertex(s, nodes[k]);
+  return rc;
 }
 
 int bal_spmv_benchmark(bal_scene *h, int32_t n_reps, double *ms_per_launch, double *bytes) {
@@ -1257,8 +1388,9 @@ int bal_step_adjoint(bal_scene *h, const double *x_t, const double *v_t, const d
   // right-hand side gx + gv / h on free body rows (grad_b holds gv, rhs holds gx + gv/h)
   hipMemsetAsync(s.grad_b.p, 0, n3 * 8, s.stream);
   hipMemsetAsync(s.rhs.p, 0, n3 * 8, s.stream);
-  hipMemcpyAsync(s.grad_b.p, gv_next, nb3 * 8, kin, s.stream);
-  hipMemcpyAsync(s.rhs.p, gx_next, nb3 * 8, kin, s.stream);
+  if ((rc = import3(s, gv_next, s.grad_b.as<double>(), s.nb, on_device != 0)) ||
+      (rc = import3(s, gx_next, s.rhs.as<double>(), s.nb, on_device != 0)))
+    return rc;
   launch_axpy_state(s, s.rhs.as<double>(), s.rhs.as<double>(), s.grad_b.as<double>(), 1.0 / s.desc.dt, (int)n3);
   // frozen state: sigma, A' (mu, s) and the active set at x_{t+1}; unprojected Hessian
   double *x = s.x.as<double>();
@@ -1302,10 +1434,12 @@ int bal_step_adjoint(bal_scene *h, const double *x_t, const double *v_t, const d
   hipLaunchKernelGGL(k_adjoint_state, dim3(blocks_for(s.N, 256)), dim3(256), 0, s.stream, s.N, lam,
                      s.grad_b.as<double>(), s.mass.as<double>(), s.freev.as<uint8_t>(), s.desc.dt, gxo.as<double>(),
                      gvo.as<double>());
+  const int status = rc;  // BAL_OK, or BAL_E_NO_CONVERGENCE of the adjoint solve
   hipMemcpyAsync(gE_accum, gEd.p, (size_t)s.T * 8, kout, s.stream);
-  hipMemcpyAsync(gx_t, gxo.p, nb3 * 8, kout, s.stream);
-  hipMemcpyAsync(gv_t, gvo.p, nb3 * 8, kout, s.stream);
-  rc = sync(s);
+  rc = export3(s, gxo.as<double>(), gx_t, s.nb, on_device != 0);
+  if (!rc) rc = export3(s, gvo.as<double>(), gv_t, s.nb, on_device != 0);
+  int rs = sync(s);
+  rc = rc ? rc : (rs ? rs : status);
   gEd.release(); gxo.release(); gvo.release(); Ed.release();
   if (stats) stats->pcg_iters = it;
   return rc;

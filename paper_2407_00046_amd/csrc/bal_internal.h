@@ -42,6 +42,10 @@ struct Scene {
   int nsv = 0, nst = 0, nse = 0;
   double cell = 0.0;    // spatial-hash cell size
   bool mixed = false;
+  // Body vertices are numbered internally in Morton order of the rest shape;
+  // perm_h[internal] = caller's index.  Obstacle vertices keep their slots.
+  std::vector<int> perm_h;
+  DBuf perm_d, stage;
   std::vector<double> mass_h;
   std::vector<uint8_t> free_h;
   std::vector<int> sv_h, st_h, se_h;
