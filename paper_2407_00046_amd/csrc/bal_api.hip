@@ -921,16 +921,42 @@ static int export3(Scene &s, const double *src, double *ext, int rows, bool on_d
 }
 static inline int ext_vertex(const Scene &s, int v) { return v < s.nb ? s.perm_h[v] : v; }
 
-// Morton order (10 bits per axis over the bounding box) of the body's rest
-// positions: vertices close in space get close indices, so the rows that share
-// matrix blocks and vector entries are processed close together and their
-// second uses meet in cache.  Returns internal -> caller index.
-static std::vector<int> morton_order(const double *X, int n) {
-  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+// Internal vertex order: the tet-connected pieces of the body one after the
+// other (in the order of their first caller index), each in Morton order
+// (10 bits per axis over the piece's own bounding box) of its rest
+// positions.  Vertices close in space get close indices, so the rows that
+// share matrix blocks and vector entries are processed close together and
+// their second uses meet in cache; keeping a piece contiguous keeps the
+// partners of its rows in the same stretch of rows (and on the same XCD,
+// which takes a contiguous stretch of the product's tiles).  Returns
+// internal -> caller index.
+static std::vector<int> morton_order(const double *X, const int32_t *tets, int n, int T) {
+  std::vector<int> root(n);
+  for (int i = 0; i < n; ++i) root[i] = i;
+  auto find = [&](int a) {
+    while (root[a] != a) a = root[a] = root[root[a]];
+    return a;
+  };
+  for (int t = 0; t < T; ++t)
+    for (int k = 1; k < 4; ++k) {
+      int a = find(tets[4 * t]), b = find(tets[4 * t + k]);
+      if (a != b) root[std::max(a, b)] = std::min(a, b);  // a piece's root is its smallest index
+    }
+  std::vector<int> piece(n, -1), first;  // piece rank in order of first index
+  for (int i = 0; i < n; ++i) {
+    int r = find(i);
+    if (piece[r] < 0) {
+      piece[r] = (int)first.size();
+      first.push_back(r);
+    }
+    piece[i] = piece[r];
+  }
+  const int np = (int)first.size();
+  std::vector<double> lo(3 * (size_t)np, INFINITY), hi(3 * (size_t)np, -INFINITY);
   for (int i = 0; i < n; ++i)
     for (int c = 0; c < 3; ++c) {
-      lo[c] = std::min(lo[c], X[3 * i + c]);
-      hi[c] = std::max(hi[c], X[3 * i + c]);
+      lo[3 * piece[i] + c] = std::min(lo[3 * piece[i] + c], X[3 * i + c]);
+      hi[3 * piece[i] + c] = std::max(hi[3 * piece[i] + c], X[3 * i + c]);
     }
   auto spread = [](uint64_t v) {  // 10 bits to every third bit
     v &= 0x3ff;
@@ -943,12 +969,13 @@ static std::vector<int> morton_order(const double *X, int n) {
   std::vector<std::pair<uint64_t, int>> key(n);
   for (int i = 0; i < n; ++i) {
     uint64_t q[3];
+    const int b = piece[i];
     for (int c = 0; c < 3; ++c) {
-      double ext = hi[c] - lo[c];
-      double f = ext > 0.0 ? (X[3 * i + c] - lo[c]) / ext : 0.0;
+      double ext = hi[3 * b + c] - lo[3 * b + c];
+      double f = ext > 0.0 ? (X[3 * i + c] - lo[3 * b + c]) / ext : 0.0;
       q[c] = (uint64_t)std::min(1023.0, std::max(0.0, std::floor(f * 1024.0)));
     }
-    key[i] = {spread(q[0]) | (spread(q[1]) << 1) | (spread(q[2]) << 2), i};
+    key[i] = {((uint64_t)b << 30) | spread(q[0]) | (spread(q[1]) << 1) | (spread(q[2]) << 2), i};
   }
   std::sort(key.begin(), key.end());
   std::vector<int> perm(n);
@@ -966,7 +993,7 @@ int bal_create_scene(const bal_scene_desc *desc, bal_scene **out) {
   try {
     // the caller's arrays in the internal vertex order
     const int nb = desc->n_verts, T = desc->n_tets;
-    std::vector<int> perm = morton_order(desc->rest_pos, nb), inv(nb);
+    std::vector<int> perm = morton_order(desc->rest_pos, desc->tets, nb, T), inv(nb);
     for (int i = 0; i < nb; ++i) inv[perm[i]] = i;
     std::vector<double> X(3 * (size_t)nb), x0, v0;
     std::vector<uint8_t> fx;

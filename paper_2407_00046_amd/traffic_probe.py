@@ -8,9 +8,12 @@ Launches, on one GPU:
      64-iteration PCG solve through bal_solve, so the k_cg_spmv dispatches
      run on a matrix of the benchmark's shape.
 
+With --workload grid, step 2 is replaced by block SpMVs on the 128^3-cell
+grid (2,146,689 nodes) in FP32 and FP64 storage.
+
 Usage (one counter group per run):
-  rocprofv3 --pmc FETCH_SIZE -d OUT -o run -- python3 paper_2407_00046_amd/traffic_probe.py
-  rocprofv3 --pmc WRITE_SIZE -d OUT -o run -- python3 paper_2407_00046_amd/traffic_probe.py
+  rocprofv3 --pmc FETCH_SIZE -d OUT -o run -- python3 paper_2407_00046_amd/traffic_probe.py [--workload grid]
+  rocprofv3 --pmc WRITE_SIZE -d OUT -o run -- python3 paper_2407_00046_amd/traffic_probe.py [--workload grid]
 """
 from __future__ import annotations
 
@@ -27,6 +30,8 @@ def main():
     ap.add_argument("--cells", type=int, default=16)
     ap.add_argument("--precision", default="mixed")
     ap.add_argument("--iters", type=int, default=64)
+    ap.add_argument("--workload", default="boxes", choices=["boxes", "grid"],
+                    help="boxes: one step of the stacked boxes then PCG; grid: products on the 128^3 grid")
     args = ap.parse_args()
     import torch
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -40,6 +45,15 @@ def main():
         b.copy_(a)
     torch.cuda.synchronize()
     print(f"[probe] copy of {args.copy_mib} MiB done", flush=True)
+    if args.workload == "grid":
+        sc = scenes.spmv_grid(128)
+        for prec in ("mixed", "fp64"):
+            g = Scene(sc, precision=prec, device=0)
+            g.linearize(np.asarray(sc["x0"]), sigma=0.0)
+            ms, by = g.spmv_benchmark(reps=5)
+            g.close()
+            print(f"[probe] grid {prec}: k_spmv {ms * 1e3:.1f} us/launch, {by:.0f} B algorithmic per SpMV", flush=True)
+        return
     sc = scenes.stacked_boxes(n_cubes=8, cells=args.cells, seed=0)
     g = Scene(sc, precision=args.precision, newton_rtol=1e-4, pcg_rtol=1e-4, device=0)
     st = g.step(allow=(0, -7))  # one step of the workload: the matrix below carries its contact blocks
