@@ -77,7 +77,7 @@ struct Scene {
   bool sigma_set = false;
   // hash scratch
   DBuf hb_lo, hb_hi, hq_lo, hq_hi, h_cnt, h_off, h_key, h_prim, h_bcnt, h_bstart, h_bfill, h_skey, h_sprim,
-      h_large, h_nlarge, h_qcnt, h_qoff, h_out, qoff_pt, out_pt, qoff_ee, out_ee;
+      h_large, h_nlarge, h_qcnt, h_lcnt, h_qoff, h_out, qoff_pt, out_pt, qoff_ee, out_ee;
   // PCG
   DBuf r, z, pv, pv2, q, pcg_ctl, warm_ctl, partial, counter, scan_tmp, red_out, flags;
   DBuf node_e, cand_e, mask, mask_off, tau, rhs, psweep;
@@ -115,7 +115,8 @@ void launch_ccd(Scene &s, const PairList &pl, const double *x, const double *p, 
 // ----- launchers (k_hash.hip)
 int build_candidates(Scene &s, PairList &out, const double *x, const double *p);
 // ----- launchers (k_linalg.hip)
-int scan_exclusive(Scene &s, const int *in, int *out, int n);  // returns total
+int scan_exclusive(Scene &s, const int *in, int *out, int n);  // returns total (synchronises), -1 on OOM
+int scan_exclusive_async(Scene &s, const int *in, int *out, int n);  // 0, or -1 on OOM
 double reduce_sum(Scene &s, const double *in, int n);
 double reduce_min(Scene &s, const double *in, int n);
 int reduce_count_less(Scene &s, const double *in, int n, double thr);

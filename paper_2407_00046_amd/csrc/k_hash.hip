@@ -8,10 +8,11 @@
 // the cells of its own box; a pair is reported only in the lowest cell of
 // the overlap of the two cell ranges, so it is found once.  Primitives
 // whose box spans more than kLargeCells cells (big obstacle faces) are kept
-// out of the grid and tested directly.  Queries count first, then write at
-// scanned offsets and sort their own segment, so the final list is in
-// canonical (kind, a, b) order with no global sort and no atomics in the
-// output.
+// out of the grid and tested directly.  Each query is served by kQG lanes
+// that split its cells' bucket entries (and its direct tests) between them;
+// queries count first, then write at scanned offsets, and the emit pass sorts
+// each query's segment, so the final list is in canonical (kind, a, b) order
+// with no global sort and no atomics in the output.
 #include "bal_internal.h"
 
 namespace bal {
@@ -20,6 +21,7 @@ constexpr int kHB = 256;
 constexpr long kLargeCells = 64;
 constexpr long kQueryCells = 4096;
 constexpr int kOff = 1 << 20;
+constexpr int kQG = 8;  // lanes per query (a power of two dividing the wave)
 // Bound on the box tests of one pass (direct tests of large entries and of
 // large queries); beyond it the pass reports BAL_E_CAPACITY and the caller
 // shortens the sweep.
@@ -169,17 +171,17 @@ __device__ bool pair_ok(const QueryArgs &A, int q, int t) {
   return !(qobs && tobs);
 }
 
-// Visits the candidate partners of query q; emit(t) for each.  For edge-edge
-// only partners t > q are reported (each unordered pair once, in the segment
-// of its smaller edge).
+// Visits the candidate partners of query q that fall to lane `lane` of the
+// query's kQG lanes; emit(t) for each.  For edge-edge only partners t > q
+// are reported (each unordered pair once, in the segment of its smaller edge).
 template <typename F>
-__device__ void visit_query(const QueryArgs &A, int q, F emit) {
+__device__ void visit_query(const QueryArgs &A, int q, int lane, F emit) {
   Box qb = prim_box(A.qtype, q, A.sv, A.st, A.se, A.x, A.p, 0.0);
   bool ee = A.qtype == 2;
   if ((ee && A.qlarge[q]) || box_cells(qb.lo, qb.hi, A.ih) > (double)kQueryCells) {
     // large query (big obstacle edge, or a box spanning too many cells):
     // direct test against every entry (every later edge for edge-edge)
-    for (int t = ee ? q + 1 : 0; t < A.ne; ++t)
+    for (int t = (ee ? q + 1 : 0) + lane; t < A.ne; t += kQG)
       if (boxes_overlap(qb, A.ebox[t]) && pair_ok(A, q, t)) emit(t);
     return;
   }
@@ -191,7 +193,7 @@ __device__ void visit_query(const QueryArgs &A, int q, F emit) {
       for (int iz = l[2]; iz <= h[2]; ++iz) {
         uint64_t k = cell_key(ix, iy, iz);
         uint32_t b = hash64(k, A.mask);
-        for (int e = A.bstart[b]; e < A.bstart[b + 1]; ++e) {
+        for (int e = A.bstart[b] + lane; e < A.bstart[b + 1]; e += kQG) {
           if (A.skey[e] != k) continue;
           int t = A.sprim[e];
           if (ee && t <= q) continue;
@@ -203,33 +205,37 @@ __device__ void visit_query(const QueryArgs &A, int q, F emit) {
           if (boxes_overlap(qb, tb) && pair_ok(A, q, t)) emit(t);
         }
       }
-  for (int k = 0; k < A.nlarge; ++k) {
+  for (int k = lane; k < A.nlarge; k += kQG) {
     int t = A.large_list[k];
     if (ee && t <= q) continue;
     if (boxes_overlap(qb, A.ebox[t]) && pair_ok(A, q, t)) emit(t);
   }
 }
 
-__global__ void k_query_count(QueryArgs A, int *qcnt) {
-  int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= A.nq) return;
+// One thread per (query, lane); the kQG lanes of a query are consecutive
+// lanes of one wave.  Writes the lane's count and the query's total.
+__global__ void k_query_count(QueryArgs A, int *lcnt, int *qcnt) {
+  int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  int q = gid / kQG, lane = gid % kQG;
+  if (q >= A.nq) return;  // whole groups leave together
   int c = 0;
-  visit_query(A, q, [&](int) { ++c; });
-  qcnt[q] = c;
+  visit_query(A, q, lane, [&](int) { ++c; });
+  lcnt[gid] = c;
+#pragma unroll
+  for (int m = kQG / 2; m > 0; m >>= 1) c += __shfl_xor(c, m, kQG);
+  if (lane == 0) qcnt[q] = c;
 }
 
-__global__ void k_query_write(QueryArgs A, const int *qoff, int *outb) {
-  int q = blockIdx.x * blockDim.x + threadIdx.x;
+// Same traversal; each lane writes at the query's offset plus the counts of
+// the lanes before it.  The segment is sorted by the emit pass.
+__global__ void k_query_write(QueryArgs A, const int *lcnt, const int *qoff, int *outb) {
+  int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  int q = gid / kQG, lane = gid % kQG;
   if (q >= A.nq) return;
   int o = qoff[q];
-  visit_query(A, q, [&](int t) { outb[o++] = t; });
-  // insertion sort of the segment (canonical order)
-  int lo = qoff[q];
-  for (int a = lo + 1; a < o; ++a) {
-    int v = outb[a], b = a - 1;
-    while (b >= lo && outb[b] > v) { outb[b + 1] = outb[b]; --b; }
-    outb[b + 1] = v;
-  }
+  const int *lc = lcnt + (size_t)q * kQG;
+  for (int k = 0; k < lane; ++k) o += lc[k];
+  visit_query(A, q, lane, [&](int t) { outb[o++] = t; });
 }
 
 // Queries whose box is tested directly against every entry.
@@ -247,11 +253,19 @@ __global__ void k_large_flag(int n, const Box *ebox, double ih, uint8_t *fl) {
   fl[i] = box_cells(b.lo, b.hi, ih) > (double)kLargeCells ? 1 : 0;
 }
 
-__global__ void k_emit_pairs(int nq, int kind, const int *qoff, const int *outb, const int *sv, const int *st,
+// Sorts each query's segment (insertion sort: segments are short) and
+// writes the pairs in canonical order.
+__global__ void k_emit_pairs(int nq, int kind, const int *qoff, int *outb, const int *sv, const int *st,
                              const int *se, int base, int *okind, int *oa, int *ob, int4 *onodes, uint64_t *okey) {
   int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= nq) return;
-  for (int k = qoff[q]; k < qoff[q + 1]; ++k) {
+  const int lo = qoff[q], hi = qoff[q + 1];
+  for (int a = lo + 1; a < hi; ++a) {
+    int v = outb[a], b = a - 1;
+    while (b >= lo && outb[b] > v) { outb[b + 1] = outb[b]; --b; }
+    outb[b + 1] = v;
+  }
+  for (int k = lo; k < hi; ++k) {
     int t = outb[k];
     int o = base + k;
     okind[o] = kind;
@@ -275,8 +289,10 @@ static int grow_pairs(PairList &pl, int n) {
 }
 
 // One half of the pass (point-triangle or edge-edge); returns the pair count
-// (negative on error) and leaves per-query offsets / partner lists in the
-// scene's scratch (h_qoff, h_out) for k_emit_pairs.
+// (negative on error) and leaves per-query offsets / partner lists in
+// qoff_buf / out_buf for k_emit_pairs.  Two host synchronisations: the entry
+// count (with the large-entry and large-query counts of the work bound) and
+// the pair count.
 static int hash_half(Scene &s, int qtype, int etype, const double *x, const double *p, int *qoff_out_n,
                      DBuf &qoff_buf, DBuf &out_buf) {
   int nq = qtype == 0 ? s.nsv : s.nse;
@@ -285,20 +301,33 @@ static int hash_half(Scene &s, int qtype, int etype, const double *x, const doub
   double infl = s.desc.dhat;
   if (s.hb_lo.grow((size_t)(ne + 1) * sizeof(Box)) || s.h_cnt.grow((size_t)(ne + 1) * sizeof(int)) ||
       s.h_off.grow((size_t)(ne + 1) * sizeof(int)) || s.h_large.grow((size_t)(ne + 1) * sizeof(int)) ||
-      s.h_nlarge.grow(2 * sizeof(int)) || s.hq_lo.grow((size_t)(nq + 1) * sizeof(uint8_t)))
+      s.h_nlarge.grow(2 * sizeof(int)) || s.hq_lo.grow((size_t)(nq + 1) * sizeof(uint8_t)) ||
+      s.h_lcnt.grow(((size_t)nq * kQG + 1) * sizeof(int)))
     return BAL_E_OOM;
   Box *ebox = s.hb_lo.as<Box>();
-  int *nlarge_d = s.h_nlarge.as<int>();
-  hipMemsetAsync(nlarge_d, 0, sizeof(int), s.stream);
+  int *nlarge_d = s.h_nlarge.as<int>();  // [0] large entries, [1] large queries
+  hipMemsetAsync(nlarge_d, 0, 2 * sizeof(int), s.stream);
   if (ne > 0)
     hipLaunchKernelGGL(k_entry_boxes, dim3(blocks_for(ne, kHB)), dim3(kHB), 0, s.stream, ne, etype, s.sv.as<int>(),
                        s.st.as<int>(), s.se.as<int>(), x, p, infl, ih, ebox, s.h_cnt.as<int>(), s.h_large.as<int>(),
                        nlarge_d);
-  int E = scan_exclusive(s, s.h_cnt.as<int>(), s.h_off.as<int>(), ne);
-  int *hn = s.pin.as<int>();
-  hipMemcpyAsync(hn, nlarge_d, sizeof(int), hipMemcpyDeviceToHost, s.stream);
-  hipStreamSynchronize(s.stream);
-  int nlarge = hn[0];
+  uint8_t *qlarge = s.hq_lo.as<uint8_t>();
+  if (qtype == 2 && ne > 0)
+    hipLaunchKernelGGL(k_large_flag, dim3(blocks_for(ne, kHB)), dim3(kHB), 0, s.stream, ne, ebox, ih, qlarge);
+  QueryArgs A{};
+  A.qtype = qtype; A.etype = etype; A.nq = nq; A.ne = ne;
+  A.sv = s.sv.as<int>(); A.st = s.st.as<int>(); A.se = s.se.as<int>();
+  A.fr = s.freev.as<uint8_t>(); A.nbody = s.nb; A.x = x; A.p = p; A.ebox = ebox; A.ih = ih;
+  A.large_list = s.h_large.as<int>(); A.qlarge = qlarge;
+  if (nq > 0)
+    hipLaunchKernelGGL(k_big_queries, dim3(blocks_for(nq, 128)), dim3(128), 0, s.stream, A, nlarge_d + 1);
+  int *hn = s.pin.as<int>() + 1024;  // clear of the slot the scan reads back
+  hipMemcpyAsync(hn, nlarge_d, 2 * sizeof(int), hipMemcpyDeviceToHost, s.stream);
+  int E = scan_exclusive(s, s.h_cnt.as<int>(), s.h_off.as<int>(), ne);  // synchronises
+  if (E < 0) return BAL_E_OOM;
+  if (ne <= 0 && hipStreamSynchronize(s.stream) != hipSuccess) return BAL_E_HIP;  // the scan returned at once
+  const int nlarge = hn[0], nbig = hn[1];
+  if ((double)nq * nlarge + (double)nbig * ne > kWorkCap) return BAL_E_CAPACITY;
   uint32_t M = 1024;
   while ((long)M < 2L * E) M <<= 1;
   if (s.h_key.grow((size_t)(E + 1) * sizeof(uint64_t)) || s.h_prim.grow((size_t)(E + 1) * sizeof(int)) ||
@@ -311,35 +340,26 @@ static int hash_half(Scene &s, int qtype, int etype, const double *x, const doub
   if (ne > 0)
     hipLaunchKernelGGL(k_entry_write, dim3(blocks_for(ne, kHB)), dim3(kHB), 0, s.stream, ne, ebox, s.h_cnt.as<int>(),
                        s.h_off.as<int>(), ih, M - 1, s.h_key.as<uint64_t>(), s.h_prim.as<int>(), s.h_bcnt.as<int>());
-  scan_exclusive(s, s.h_bcnt.as<int>(), s.h_bstart.as<int>(), (int)M + 1);
+  if (scan_exclusive_async(s, s.h_bcnt.as<int>(), s.h_bstart.as<int>(), (int)M + 1)) return BAL_E_OOM;
   if (E > 0)
     hipLaunchKernelGGL(k_entry_scatter, dim3(blocks_for(E, kHB)), dim3(kHB), 0, s.stream, E, s.h_key.as<uint64_t>(),
                        s.h_prim.as<int>(), M - 1, s.h_bstart.as<int>(), s.h_bfill.as<int>(), s.h_skey.as<uint64_t>(),
                        s.h_sprim.as<int>());
-  uint8_t *qlarge = s.hq_lo.as<uint8_t>();
-  if (qtype == 2 && ne > 0)
-    hipLaunchKernelGGL(k_large_flag, dim3(blocks_for(ne, kHB)), dim3(kHB), 0, s.stream, ne, ebox, ih, qlarge);
-  QueryArgs A;
-  A.qtype = qtype; A.etype = etype; A.nq = nq; A.ne = ne;
-  A.sv = s.sv.as<int>(); A.st = s.st.as<int>(); A.se = s.se.as<int>();
-  A.fr = s.freev.as<uint8_t>(); A.nbody = s.nb; A.x = x; A.p = p; A.ebox = ebox; A.ih = ih; A.mask = M - 1;
+  A.mask = M - 1;
   A.bstart = s.h_bstart.as<int>(); A.skey = s.h_skey.as<uint64_t>(); A.sprim = s.h_sprim.as<int>();
-  A.large_list = s.h_large.as<int>(); A.nlarge = nlarge; A.qlarge = qlarge;
-  if (nq > 0) {
-    hipMemsetAsync(nlarge_d + 1, 0, sizeof(int), s.stream);
-    hipLaunchKernelGGL(k_big_queries, dim3(blocks_for(nq, 128)), dim3(128), 0, s.stream, A, nlarge_d + 1);
-    hipMemcpyAsync(hn, nlarge_d + 1, sizeof(int), hipMemcpyDeviceToHost, s.stream);
-    hipStreamSynchronize(s.stream);
-    if ((double)nq * nlarge + (double)hn[0] * ne > kWorkCap) return BAL_E_CAPACITY;
-  }
+  A.nlarge = nlarge;
   if (s.h_qcnt.grow((size_t)(nq + 1) * sizeof(int)) || qoff_buf.grow((size_t)(nq + 1) * sizeof(int))) return BAL_E_OOM;
   hipMemsetAsync(s.h_qcnt.p, 0, (nq + 1) * sizeof(int), s.stream);
-  if (nq > 0) hipLaunchKernelGGL(k_query_count, dim3(blocks_for(nq, 128)), dim3(128), 0, s.stream, A, s.h_qcnt.as<int>());
-  int P = scan_exclusive(s, s.h_qcnt.as<int>(), qoff_buf.as<int>(), nq + 1);
+  const int qthreads = nq * kQG;  // nq * kQG < 2^31: nq is a surface count
+  if (nq > 0)
+    hipLaunchKernelGGL(k_query_count, dim3(blocks_for(qthreads, kHB)), dim3(kHB), 0, s.stream, A,
+                       s.h_lcnt.as<int>(), s.h_qcnt.as<int>());
+  int P = scan_exclusive(s, s.h_qcnt.as<int>(), qoff_buf.as<int>(), nq + 1);  // synchronises
+  if (P < 0) return BAL_E_OOM;
   if (out_buf.grow((size_t)(P + 1) * sizeof(int))) return BAL_E_OOM;
   if (nq > 0 && P > 0)
-    hipLaunchKernelGGL(k_query_write, dim3(blocks_for(nq, 128)), dim3(128), 0, s.stream, A, qoff_buf.as<int>(),
-                       out_buf.as<int>());
+    hipLaunchKernelGGL(k_query_write, dim3(blocks_for(qthreads, kHB)), dim3(kHB), 0, s.stream, A,
+                       s.h_lcnt.as<int>(), qoff_buf.as<int>(), out_buf.as<int>());
   *qoff_out_n = nq;
   return P;
 }

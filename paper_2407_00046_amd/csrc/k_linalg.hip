@@ -170,7 +170,7 @@ __global__ void k_scan_add(int *__restrict__ out, int n, const int *__restrict__
   }
 }
 
-int scan_exclusive(Scene &s, const int *in, int *out, int n) {
+int scan_exclusive_async(Scene &s, const int *in, int *out, int n) {
   if (n <= 0) return 0;
   int nb = blocks_for(n, kBS * kScanItems);
   if (s.scan_tmp.grow((size_t)(nb + 2) * sizeof(int))) return -1;
@@ -179,6 +179,13 @@ int scan_exclusive(Scene &s, const int *in, int *out, int n) {
   hipLaunchKernelGGL(k_scan_block, dim3(nb), dim3(kBS), 0, s.stream, in, out, n, sums);
   hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kBS), 0, s.stream, sums, nb, total);
   hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(kBS), 0, s.stream, out, n, sums);
+  return 0;
+}
+
+int scan_exclusive(Scene &s, const int *in, int *out, int n) {
+  if (n <= 0) return 0;
+  if (scan_exclusive_async(s, in, out, n)) return -1;
+  int *total = s.scan_tmp.as<int>();
   int *h = s.pin.as<int>();
   hipMemcpyAsync(h, total, sizeof(int), hipMemcpyDeviceToHost, s.stream);
   hipStreamSynchronize(s.stream);

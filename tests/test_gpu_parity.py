@@ -149,6 +149,79 @@ def test_candidates_cover_active_pairs(contact_case):
             assert key(pairs.kind[i], pairs.nodes[i]) in got2
 
 
+def box_overlap_candidates(x, p, sv, st, se, free, n_body, dhat):
+    """The candidate set by its definition, brute force: every point-triangle
+    and edge-edge pair of surface primitives with no shared vertex, some free
+    vertex and not both on obstacles, whose boxes over [x, x + p] overlap once
+    one of the two is inflated by dhat (the same FP64 operations as the
+    library's box test, so the set is exact)."""
+    e = x if p is None else x + p
+    lo_v, hi_v = np.minimum(x, e), np.maximum(x, e)
+
+    def boxes(prims, infl):
+        return lo_v[prims].min(axis=1) - infl, hi_v[prims].max(axis=1) + infl
+
+    out = set()
+    # point-triangle: vertex box against the inflated triangle box
+    vlo, vhi = boxes(sv[:, None], 0.0)
+    tlo, thi = boxes(st, dhat)
+    ov = np.all((tlo[None] <= vhi[:, None]) & (vlo[:, None] <= thi[None]), axis=2)
+    for i, j in zip(*np.nonzero(ov)):
+        v, tri = int(sv[i]), tuple(sorted(map(int, st[j])))
+        if v in tri or not (free[v] or any(free[t] for t in tri)) or (v >= n_body and tri[0] >= n_body):
+            continue
+        out.add((0, v, tri))
+    # edge-edge: first edge's box against the second's inflated box
+    alo, ahi = boxes(se, 0.0)
+    blo, bhi = boxes(se, dhat)
+    ov = np.all((blo[None] <= ahi[:, None]) & (alo[:, None] <= bhi[None]), axis=2)
+    for i, j in zip(*np.nonzero(np.triu(ov, 1))):
+        a, b = tuple(sorted(map(int, se[i]))), tuple(sorted(map(int, se[j])))
+        if set(a) & set(b) or not any(free[v] for v in a + b) or (min(a) >= n_body and min(b) >= n_body):
+            continue
+        out.add((1, tuple(sorted([a, b]))))
+    return out
+
+
+def candidate_keys(kind, nodes):
+    keys = []
+    for k, nd in zip(kind, nodes):
+        nd = list(map(int, nd))
+        keys.append((0, nd[0], tuple(sorted(nd[1:]))) if k == 0 else
+                    (1, tuple(sorted([tuple(sorted(nd[:2])), tuple(sorted(nd[2:]))]))))
+    return keys
+
+
+@pytest.mark.parametrize("case", ["tiny_cube", "two_boxes"])
+def test_candidates_equal_box_overlap_set(case):
+    """The spatial-hash pass returns exactly the box-overlap candidate set,
+    each pair once, at rest and along a swept displacement."""
+    if case == "tiny_cube":
+        sc = scenes.tiny_cube()
+        o, x, _, _, _ = contact_state(sc)
+        x = np.concatenate([x[: o.n_body], np.asarray(sc["obs_pos"]).reshape(-1, 3)])
+    else:
+        sc = scenes.stacked_boxes(n_cubes=2, cells=6, seed=0)
+        x = np.concatenate([sc["x0"], np.asarray(sc["obs_pos"]).reshape(-1, 3)])
+    nb = sc["rest_pos"].shape[0]
+    g = lib_scene(sc)
+    sv, st, se = g.surface()
+    free = np.concatenate([sc["fixed"] == 0, np.zeros(x.shape[0] - nb, bool)])
+    rng = np.random.default_rng(9)
+    for scale in (0.0, 2e-3, 2e-2):
+        p = None
+        if scale > 0:
+            p = np.zeros_like(x)
+            p[:nb] = rng.normal(scale=scale, size=(nb, 3))
+            p[:nb, 1] -= scale
+        kind, nodes, _ = g.candidates(x, p)
+        got = candidate_keys(kind, nodes)
+        ref = box_overlap_candidates(x, p, sv, st, se, free, nb, sc["dhat"])
+        print(f"{case} sweep {scale}: {len(got)} candidates, {len(ref)} by definition")
+        assert len(set(got)) == len(got)
+        assert set(got) == ref
+
+
 def test_ccd_bound(contact_case):
     sc, o, x, y, pairs, st = contact_case
     g = lib_scene(sc)
