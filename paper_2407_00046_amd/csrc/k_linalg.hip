@@ -561,9 +561,23 @@ struct VecDir {
   const VT *__restrict__ z;
   const VT *__restrict__ p;
   double beta;
-  __device__ __forceinline__ void load(int j, VT *w) const {
+  // the two halves of load(): the raw entries (issued before beta is
+  // known) and the combination
+  __device__ __forceinline__ void raw(int j, VT *zr, VT *pr) const {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) w[c] = (VT)((double)z[3 * j + c] + beta * (double)p[3 * j + c]);
+    for (int c = 0; c < 3; ++c) {
+      zr[c] = z[3 * j + c];
+      pr[c] = p[3 * j + c];
+    }
+  }
+  __device__ __forceinline__ void form(const VT *zr, const VT *pr, VT *w) const {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) w[c] = (VT)((double)zr[c] + beta * (double)pr[c]);
+  }
+  __device__ __forceinline__ void load(int j, VT *w) const {
+    VT zr[3], pr[3];
+    raw(j, zr, pr);
+    form(zr, pr, w);
   }
 };
 
@@ -588,8 +602,9 @@ __device__ __forceinline__ void blk_mtv(const MT *__restrict__ a, const VT *w, V
 // arithmetic, so that a typical row costs two rounds of memory latency.
 // `pre` runs (on every thread of the block) after the first pass's index
 // and block loads and the diagonal block load are issued and before any
-// operand entry is read; it may set up the operand (the CG direction's beta)
-// and returns false to abandon the product.
+// operand entry is read; it returns false to abandon the product.  (The PCG
+// product launch has its own copy of this loop, which also issues the first
+// pass's raw operand entries before its scalars are known.)
 constexpr int kU = 3;
 
 template <typename MT>
@@ -902,25 +917,39 @@ __device__ __forceinline__ void update_partial(int N, int i, const uint8_t *fr, 
 }
 
 // ---- global solve
-// Sums of up to three partial arrays with every thread of the block: each
-// thread issues all of its loads before adding them (in a fixed order), then
-// a fixed shuffle tree per wave and the waves in order.  The partial arrays
-// here hold a few hundred entries, so one round of loads covers them.
+// Sums of up to three partial arrays with every thread of the block, in two
+// halves so that a kernel can issue the loads early: sums_load issues the
+// first round (four per thread per array), sums_finish adds them in a fixed
+// order (and any further rounds), then a fixed shuffle tree per wave and the
+// waves in order.  The partial arrays here hold a few hundred entries, so one
+// round of loads covers them.
 template <int NS>
-__device__ void block_sums(const double *const *src, const int *n, double *out) {
-  constexpr int kU = 4;
+__device__ __forceinline__ void sums_load(const double *const *src, const int *n, double (&v)[NS][4]) {
+#pragma unroll
+  for (int m = 0; m < NS; ++m)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int j = threadIdx.x + u * kBS;
+      v[m][u] = j < n[m] ? src[m][j] : 0.0;
+    }
+}
+
+template <int NS>
+__device__ void sums_finish(const double *const *src, const int *n, const double (&v)[NS][4], double *out) {
   __shared__ double sh[NS][kBS / 64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   double acc[NS];
 #pragma unroll
   for (int m = 0; m < NS; ++m) {
     acc[m] = 0.0;
-    for (int j0 = threadIdx.x; j0 < n[m]; j0 += kU * kBS) {
-      double v[kU];
 #pragma unroll
-      for (int u = 0; u < kU; ++u) v[u] = j0 + u * kBS < n[m] ? src[m][j0 + u * kBS] : 0.0;
+    for (int u = 0; u < 4; ++u) acc[m] += v[m][u];
+    for (int j0 = threadIdx.x + 4 * kBS; j0 < n[m]; j0 += 4 * kBS) {
+      double x[4];
 #pragma unroll
-      for (int u = 0; u < kU; ++u) acc[m] += v[u];
+      for (int u = 0; u < 4; ++u) x[u] = j0 + u * kBS < n[m] ? src[m][j0 + u * kBS] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[m] += x[u];
     }
   }
 #pragma unroll
@@ -940,14 +969,24 @@ __device__ void block_sums(const double *const *src, const int *n, double *out) 
   __syncthreads();  // sh is reused by the next call
 }
 
+template <int NS>
+__device__ void block_sums(const double *const *src, const int *n, double *out) {
+  double v[NS][4];
+  sums_load<NS>(src, n, v);
+  sums_finish<NS>(src, n, v, out);
+}
+
 // Iteration k, first launch.  Unless this is the first iteration (previous
 // slot marked it = -1, state 0 written by the initialisation), forms the
 // state after iteration k from the previous partials and applies the
 // stopping rules (App. B: relative residual, stagnation over the window, cap;
 // p.q <= 0 is a breakdown); block 0 stores it in slot k & 1.  Then
 // p_k = z + beta_k p_{k-1} (the row owner stores it), q = A p_k and the
-// partial p_k.q.  p is double-buffered (p_new never aliases p_old) and so is
-// the p.q partial array (this launch reads one and writes the other).
+// partial p_k.q.  The partial loads are issued first, then the row's
+// indices, blocks and the raw z and p_{k-1} entries of its first pass; beta
+// is formed while these are in flight.  p is double-buffered (p_new never
+// aliases p_old) and so is the p.q partial array (this launch reads one and
+// writes the other).
 template <typename MT, typename VT>
 __global__ __launch_bounds__(kBS) void k_cg_dir_spmv(int N, int k, BsrView<MT> B, const VT *__restrict__ z,
                                                      const VT *__restrict__ p_old, VT *__restrict__ p_new,
@@ -957,18 +996,39 @@ __global__ __launch_bounds__(kBS) void k_cg_dir_spmv(int N, int k, BsrView<MT> B
   const CgSlot &prev = ctl->slot[(k - 1) & 1];
   const bool first = prev.it < 0;
   if (first ? ctl->slot[k & 1].done : prev.done) return;
+  const double *src[3] = {part, part + nb, part_pq_prev};
+  const int cnt[3] = {nb, nb, (int)gridDim.x};
+  double pv[3][4];
+  if (!first) sums_load<3>(src, cnt, pv);
   const int tile = xcd_tile();
-  long t = (long)tile * blockDim.x + threadIdx.x;
-  int i = (int)(t / kG), g = (int)(t % kG);
+  const long t = (long)tile * blockDim.x + threadIdx.x;
+  const int i = t / kG < N ? (int)(t / kG) : -1, g = (int)(t % kG);
   VecDir<VT> dir{z, first ? z : p_old, 0.0};  // p_0 = z_0: beta = 0 must not meet an unset buffer
-  // the state after iteration k and beta_k, from the previous partials; runs
-  // while the row's first index and block loads are in flight
-  auto state = [&]() -> bool {
-    if (first) return true;
+  VT acc[3] = {(VT)0, (VT)0, (VT)0};
+  int l0 = 0, nl = 0, u0 = 0, nt = 0, c0 = 0, c1 = 0;
+  RowBatch<MT> rb;
+  MT dblk[9];
+  VT zr[kU][3], pr[kU][3];
+  if (i >= 0) {
+    l0 = B.rp[i];
+    nl = B.rp[i + 1] - l0;
+    u0 = B.up[i];
+    nt = nl + B.up[i + 1] - u0;
+    c0 = B.cp[i];
+    c1 = B.cp[i + 1];
+    row_fetch<MT>(i, g, l0, nl, u0, nt, B, rb);
+    if (g == 0) {
+#pragma unroll
+      for (int c = 0; c < 9; ++c) dblk[c] = B.D[(size_t)9 * i + c];
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+      if (rb.on[u]) dir.raw(rb.j[u], zr[u], pr[u]);
+  }
+  if (!first) {
+    // the state after iteration k and beta_k
     double tv[3];
-    const double *src[3] = {part, part + nb, part_pq_prev};
-    const int cnt[3] = {nb, nb, (int)gridDim.x};
-    block_sums<3>(src, cnt, tv);
+    sums_finish<3>(src, cnt, pv, tv);
     const double rz = tv[0], rr = tv[1], pq = tv[2];
     const int it = prev.it + 1;
     const double rn = sqrt(rr);
@@ -991,14 +1051,44 @@ __global__ __launch_bounds__(kBS) void k_cg_dir_spmv(int N, int k, BsrView<MT> B
       o.done = done;
       if (done) ctl->stop = 1;  // later launches exit at once
     }
+    if (done) return;
     dir.beta = prev.rz != 0.0 ? rz / prev.rz : 0.0;
-    return !done;
-  };
+  }
+  if (i >= 0) {
+    for (int tt = g;;) {
+      VT w[kU][3];
+#pragma unroll
+      for (int u = 0; u < kU; ++u)
+        if (rb.on[u]) dir.form(zr[u], pr[u], w[u]);
+#pragma unroll
+      for (int u = 0; u < kU; ++u)
+        if (rb.on[u]) {
+          if (rb.tr[u]) blk_mtv<MT, VT>(rb.a[u], w[u], acc);
+          else blk_mv<MT, VT>(rb.a[u], w[u], acc);
+        }
+      tt += kU * kG;
+      if (tt >= nt) break;
+      row_fetch<MT>(i, tt, l0, nl, u0, nt, B, rb);
+#pragma unroll
+      for (int u = 0; u < kU; ++u)
+        if (rb.on[u]) dir.raw(rb.j[u], zr[u], pr[u]);
+    }
+    for (int c = c0 + g; c < c1; c += kG) {
+      VT w0[3];
+      dir.load(B.cc[c], w0);
+      blk_mv<MT, VT>(B.pblk + (size_t)9 * B.cs[c], w0, acc);
+    }
+  }
+#pragma unroll
+  for (int o = kG / 2; o > 0; o >>= 1)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc[c] += __shfl_xor(acc[c], o, kG);
   double vals[1] = {0.0};
   int bin = -1;
-  VT acc[3], own[3];
-  if (!spmv_row_pre<MT, VT, false>(i < N ? i : -1, g, B, nullptr, dir, state, acc, own)) return;
-  if (i < N && g == 0) {
+  if (i >= 0 && g == 0) {
+    VT own[3];
+    dir.load(i, own);
+    blk_mv<MT, VT>(dblk, own, acc);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       p_new[3 * i + c] = own[c];
@@ -1021,8 +1111,9 @@ __global__ __launch_bounds__(kBS) void k_cg_update(int N, int k, const uint8_t *
   const CgSlot &s = ctl->slot[k & 1];
   if (ctl->stop || s.done) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  // the p.q partials are loaded first, then the node's operands, which are
+  // in flight while the partials are summed
   const bool act = i < N && fr[i];
-  // the node's operands are loaded while the p.q partials are summed
   double pv[3] = {0.0, 0.0, 0.0}, qv[3] = {0.0, 0.0, 0.0}, xv[3] = {0.0, 0.0, 0.0}, rv[3] = {0.0, 0.0, 0.0};
   MT d[9];
   if (act) {
