@@ -865,26 +865,6 @@ struct WarmCtl {
 };
 
 // ---- shared pieces
-template <typename MT, typename VT, int NB>
-__device__ __forceinline__ void spmv_partial(int N, const BsrView<MT> &B, const int *grp, const VT *p, VT *q,
-                                             double *part) {
-  const int tile = xcd_tile();
-  long t = (long)tile * blockDim.x + threadIdx.x;
-  double vals[1] = {0.0};
-  int bin = -1;
-  int i = (int)(t / kG), g = (int)(t % kG);
-  VT acc[3], own[3];
-  spmv_row<MT, VT, (NB > 1)>(i < N ? i : -1, g, B, grp, VecPlain<VT>{p}, acc, own);
-  if (i < N && g == 0) {
-    q[3 * i] = acc[0];
-    q[3 * i + 1] = acc[1];
-    q[3 * i + 2] = acc[2];
-    bin = bin_of<NB>(grp, i);
-    vals[0] = (double)own[0] * (double)acc[0] + (double)own[1] * (double)acc[1] + (double)own[2] * (double)acc[2];
-  }
-  block_partials<NB, 1>(bin, vals, part, tile);
-}
-
 // x += al p ; r -= al q ; z = Dinv r ; partial r.z and r.r
 template <typename MT, typename VT, int NB>
 __device__ __forceinline__ void update_partial(int N, int i, const uint8_t *fr, const MT *Dinv, const int *grp,
@@ -1154,13 +1134,92 @@ __global__ __launch_bounds__(kBS) void k_cg_update(int N, int k, const uint8_t *
   block_partials<1, 2>(bin, vals, part, blockIdx.x);
 }
 
-// ---- warm start (per-group bins)
+// ---- warm start (per-group bins), three launches per iteration
+//   k_w_dir_spmv  the stop decision from the per-bin state of the previous
+//                 iteration (every block, same inputs; block 0 records it),
+//                 then p = z + beta_bin p_old formed where it is read (the
+//                 row owner stores p; p is double-buffered), q = the
+//                 group-masked product and the per-bin partials p.q
+//   k_w_update    alpha of every bin present in the block, summed from that
+//                 bin's p.q partials; x += alpha p, r -= alpha q,
+//                 z = D^{-1} r, per-bin partials r.z and r.r
+//   k_w_beta      one block per bin: beta, rz, rr and the bin's tolerance
+//                 test; block 0 also counts the iteration
 template <typename MT, typename VT>
-__global__ __launch_bounds__(kBS) void k_w_spmv(int N, BsrView<MT> B, const int *__restrict__ grp,
-                                                const VT *__restrict__ p, VT *__restrict__ q, const WarmCtl *ctl,
-                                                double *part) {
+__global__ __launch_bounds__(kBS) void k_w_dir_spmv(int N, BsrView<MT> B, const int *__restrict__ grp,
+                                                    const VT *__restrict__ z, const VT *__restrict__ p_old,
+                                                    VT *__restrict__ p_new, VT *__restrict__ q, WarmCtl *ctl,
+                                                    double *part_pq) {
   if (ctl->done) return;
-  spmv_partial<MT, VT, kGroups>(N, B, grp, p, q, part);
+  int any = 0;
+  for (int b = 0; b < kGroups; ++b) any |= ctl->active[b];
+  const int it = ctl->it;
+  const int done = !any ? PCG_CONVERGED : (it >= ctl->max_it ? PCG_CAPPED : PCG_RUN);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    double rr = 0.0;
+    for (int b = 0; b < kGroups; ++b) rr += ctl->rr[b];
+    ctl->rnorm = sqrt(rr);
+    if (done) ctl->done = done;
+  }
+  if (done) return;
+  const int tile = xcd_tile();
+  const long t = (long)tile * blockDim.x + threadIdx.x;
+  const int i = t / kG < N ? (int)(t / kG) : -1, g = (int)(t % kG);
+  // p_0 = z_0: beta = 0 must not meet an unset buffer
+  const bool first = it == 0;
+  VecDir<VT> dir{z, first ? z : p_old, (i >= 0 && !first) ? ctl->beta[bin_of<kGroups>(grp, i)] : 0.0};
+  double vals[1] = {0.0};
+  int bin = -1;
+  VT acc[3], own[3];
+  spmv_row<MT, VT, true>(i, g, B, grp, dir, acc, own);
+  if (i >= 0 && g == 0) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      p_new[3 * i + c] = own[c];
+      q[3 * i + c] = acc[c];
+    }
+    bin = bin_of<kGroups>(grp, i);
+    vals[0] = (double)own[0] * (double)acc[0] + (double)own[1] * (double)acc[1] + (double)own[2] * (double)acc[2];
+  }
+  block_partials<kGroups, 1>(bin, vals, part_pq, tile);
+}
+
+template <typename MT, typename VT>
+__global__ __launch_bounds__(kBS) void k_w_update(int N, int nbs, const uint8_t *__restrict__ fr,
+                                                  const MT *__restrict__ Dinv, const int *__restrict__ grp,
+                                                  const VT *__restrict__ p, const VT *__restrict__ q,
+                                                  double *__restrict__ x, double *__restrict__ r, VT *__restrict__ z,
+                                                  WarmCtl *ctl, const double *part_pq, double *part) {
+  if (ctl->done) return;
+  __shared__ unsigned present[kGroups / 32];
+  __shared__ double alpha_sh[kGroups];
+  if (threadIdx.x < kGroups / 32) present[threadIdx.x] = 0u;
+  __syncthreads();
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N && fr[i]) {
+    const int b = bin_of<kGroups>(grp, i);
+    atomicOr(&present[b >> 5], 1u << (b & 31));
+  }
+  __syncthreads();
+  // alpha of each bin present here, from that bin's p.q partials (the same
+  // sums, in the same order, in every block that holds the bin)
+  for (int w = 0; w < kGroups / 32; ++w) {
+    unsigned m = present[w];
+    while (m) {
+      const int b = 32 * w + __builtin_ctz(m);
+      m &= m - 1;
+      const double *src[1] = {part_pq + (size_t)b * nbs};
+      double pq;
+      block_sums<1>(src, &nbs, &pq);
+      if (threadIdx.x == 0) {
+        const bool act = ctl->active[b] != 0, ok = pq > 0.0;
+        alpha_sh[b] = act && ok ? ctl->rz[b] / pq : 0.0;
+        if (act && !ok) ctl->active[b] = 0;  // breakdown: the bin stops (same value from every block)
+      }
+    }
+  }
+  __syncthreads();
+  update_partial<MT, VT, kGroups>(N, i, fr, Dinv, grp, p, q, x, r, z, alpha_sh, part);
 }
 
 // One block per group bin: the sum of that bin's partials (bin-major
@@ -1172,35 +1231,10 @@ __device__ double bin_sum(const double *part, int nbk, int k) {
   return out;
 }
 
-__global__ void k_w_alpha(int nbk, WarmCtl *ctl, const double *part) {
-  const int b = blockIdx.x;
-  if (ctl->done) return;
-  if (!ctl->active[b]) {
-    if (threadIdx.x == 0) ctl->alpha[b] = 0.0;
-    return;
-  }
-  double pq = bin_sum(part, nbk, b);
-  if (threadIdx.x == 0) {
-    bool ok = pq > 0.0;
-    ctl->alpha[b] = ok ? ctl->rz[b] / pq : 0.0;
-    if (!ok) ctl->active[b] = 0;
-  }
-}
-
-template <typename MT, typename VT>
-__global__ __launch_bounds__(kBS) void k_w_update(int N, const uint8_t *__restrict__ fr, const MT *__restrict__ Dinv,
-                                                  const int *__restrict__ grp, const VT *__restrict__ p,
-                                                  const VT *__restrict__ q, double *__restrict__ x,
-                                                  double *__restrict__ r, VT *__restrict__ z, const WarmCtl *ctl,
-                                                  double *part) {
-  if (ctl->done) return;
-  update_partial<MT, VT, kGroups>(N, blockIdx.x * blockDim.x + threadIdx.x, fr, Dinv, grp, p, q, x, r, z, ctl->alpha,
-                                  part);
-}
-
 __global__ void k_w_beta(int nbk, WarmCtl *ctl, const double *part) {
   const int b = blockIdx.x;
   if (ctl->done) return;
+  if (b == 0 && threadIdx.x == 0) ctl->it += 1;  // read by the next launch only
   if (!ctl->active[b]) {
     if (threadIdx.x == 0) ctl->beta[b] = 0.0;
     return;
@@ -1212,38 +1246,6 @@ __global__ void k_w_beta(int nbk, WarmCtl *ctl, const double *part) {
     ctl->rr[b] = rr;
     if (rr <= ctl->tol2 * ctl->ref2[b]) ctl->active[b] = 0;
   }
-}
-
-// After the per-bin updates: iteration count, total residual and the stop
-// decision (one thread); kept apart so that every block of the direction
-// update below reads the same decision.
-__device__ void warm_bookkeeping(WarmCtl *ctl) {
-  double rr = 0.0;
-  int any = 0;
-  for (int b = 0; b < kGroups; ++b) {
-    rr += ctl->rr[b];
-    any |= ctl->active[b];
-  }
-  ctl->rnorm = sqrt(rr);
-  ctl->it += 1;
-  if (!any) ctl->done = PCG_CONVERGED;
-  else if (ctl->it >= ctl->max_it) ctl->done = PCG_CAPPED;
-}
-
-__global__ void k_w_check(WarmCtl *ctl) {
-  if (ctl->done || threadIdx.x != 0) return;
-  warm_bookkeeping(ctl);
-}
-
-template <typename VT>
-__global__ void k_w_dir(int N, const int *__restrict__ grp, const VT *__restrict__ z, VT *__restrict__ p,
-                        const WarmCtl *ctl) {
-  if (ctl->done) return;
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  double be = ctl->beta[bin_of<kGroups>(grp, i)];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) p[3 * i + c] = (VT)((double)z[3 * i + c] + be * (double)p[3 * i + c]);
 }
 
 // ---- initialisation: r = b - q (q = A x0 or zero), z = Dinv r, p = z;
@@ -1535,10 +1537,15 @@ static int cg_run(Scene &s, const double *rhs, double *xsol, double tol, double 
 template <typename MT, typename VT>
 static int warm_run(Scene &s, const double *rhs, double *xsol, double tol, int max_iters, int *iters_out) {
   int N = s.N, nb = blocks_for(N, kBS), nbs = spmv_grid(N);
-  if (s.partial.grow((size_t)nbs * 3 * kGroups * sizeof(double)) || s.warm_ctl.grow(sizeof(WarmCtl))) return BAL_E_OOM;
-  double *part = s.partial.as<double>();
+  // per-bin partials: r.z, r.r, b.b of the update (and the initialisation),
+  // then p.q of the product
+  if (s.partial.grow(((size_t)3 * kGroups * nb + (size_t)kGroups * nbs) * sizeof(double)) ||
+      s.warm_ctl.grow(sizeof(WarmCtl)) || s.pv2.grow((size_t)3 * N * sizeof(VT)))
+    return BAL_E_OOM;
+  double *part = s.partial.as<double>(), *part_pq = part + (size_t)3 * kGroups * nb;
   WarmCtl *ctl = s.warm_ctl.as<WarmCtl>();
-  VT *p = static_cast<VT *>(s.pv.p), *q = static_cast<VT *>(s.q.p), *z = static_cast<VT *>(s.z.p);
+  VT *pb[2] = {static_cast<VT *>(s.pv.p), static_cast<VT *>(s.pv2.p)};
+  VT *q = static_cast<VT *>(s.q.p), *z = static_cast<VT *>(s.z.p);
   const BsrView<MT> B = bsr_view<MT>(s);
   const MT *Dinv = static_cast<const MT *>(s.Dinv.p);
   const int *grp = s.group.as<int>();
@@ -1547,26 +1554,27 @@ static int warm_run(Scene &s, const double *rhs, double *xsol, double tol, int m
   hipLaunchKernelGGL(k_w_init_bins, dim3(kGroups), dim3(kBS), 0, s.stream, nb, ctl, part, tol * tol);
   hipLaunchKernelGGL(k_w_init_done, dim3(1), dim3(64), 0, s.stream, ctl, tol * tol, max_iters);
   WarmCtl *h = s.pin.as<WarmCtl>();
+  // iterations go in whole chunks of an even count, so iteration c of a
+  // chunk has the parity of c
   const int chunk = 8;
-  auto launch_iter = [&]() {
-    hipLaunchKernelGGL((k_w_spmv<MT, VT>), dim3(nbs), dim3(kBS), 0, s.stream, N, B, grp, p, q, ctl, part);
-    hipLaunchKernelGGL(k_w_alpha, dim3(kGroups), dim3(kBS), 0, s.stream, nbs, ctl, part);
-    hipLaunchKernelGGL((k_w_update<MT, VT>), dim3(nb), dim3(kBS), 0, s.stream, N, s.freev.as<uint8_t>(), Dinv, grp, p,
-                       q, xsol, r, z, ctl, part);
+  auto launch_iter = [&](int c) {
+    VT *pnew = pb[c & 1], *pold = pb[(c & 1) ^ 1];
+    hipLaunchKernelGGL((k_w_dir_spmv<MT, VT>), dim3(nbs), dim3(kBS), 0, s.stream, N, B, grp, z, pold, pnew, q, ctl,
+                       part_pq);
+    hipLaunchKernelGGL((k_w_update<MT, VT>), dim3(nb), dim3(kBS), 0, s.stream, N, nbs, s.freev.as<uint8_t>(), Dinv,
+                       grp, pnew, q, xsol, r, z, ctl, part_pq, part);
     hipLaunchKernelGGL(k_w_beta, dim3(kGroups), dim3(kBS), 0, s.stream, nb, ctl, part);
-    hipLaunchKernelGGL(k_w_check, dim3(1), dim3(64), 0, s.stream, ctl);
-    hipLaunchKernelGGL((k_w_dir<VT>), dim3(nb), dim3(kBS), 0, s.stream, N, grp, z, p, ctl);
   };
   std::vector<uintptr_t> sig = bsr_sig(B);
-  sig.insert(sig.end(), {(uintptr_t)grp, (uintptr_t)p, (uintptr_t)q, (uintptr_t)ctl, (uintptr_t)part,
-                         (uintptr_t)s.freev.p, (uintptr_t)Dinv, (uintptr_t)xsol, (uintptr_t)r, (uintptr_t)z,
-                         (uintptr_t)N});
+  sig.insert(sig.end(), {(uintptr_t)grp, (uintptr_t)pb[0], (uintptr_t)pb[1], (uintptr_t)q, (uintptr_t)ctl,
+                         (uintptr_t)part, (uintptr_t)s.freev.p, (uintptr_t)Dinv, (uintptr_t)xsol, (uintptr_t)r,
+                         (uintptr_t)z, (uintptr_t)N});
   for (;;) {
     bool graphed = false;
     if (s.use_graphs) {
       if (!graph_current(s.warm_sig, sig, s.warm_exec)) {
         bool ok = capture_graph(s, s.warm_exec, [&]() {
-          for (int c = 0; c < chunk; ++c) launch_iter();
+          for (int c = 0; c < chunk; ++c) launch_iter(c);
         });
         if (ok) s.warm_sig = sig; else { s.use_graphs = false; s.warm_sig.clear(); }
       }
@@ -1576,7 +1584,7 @@ static int warm_run(Scene &s, const double *rhs, double *xsol, double tol, int m
       }
     }
     if (!graphed)
-      for (int c = 0; c < chunk; ++c) launch_iter();
+      for (int c = 0; c < chunk; ++c) launch_iter(c);
     hipMemcpyAsync(h, ctl, sizeof(WarmCtl), hipMemcpyDeviceToHost, s.stream);
     if (hipStreamSynchronize(s.stream) != hipSuccess) return BAL_E_HIP;
     if (h->done) break;
