@@ -768,6 +768,19 @@ static int build_scene(Scene &s, const bal_scene_desc *d) {
     for (int i = 0; i < N; ++i)
       for (int k = rp[i]; k < rp[i + 1]; ++k) upe[fill[ci[k]]++] = make_int2(i, k);
   }
+  // FP32 storage also keeps one entry list per row: (column, block) of its
+  // lower blocks, then (row, block) of its transposed ones; a dummy entry
+  // (operand 0, the spare block) closes the list
+  std::vector<int2> entl;
+  if (s.mixed) {
+    entl.resize((size_t)2 * s.nnzb + 1);
+    size_t o = 0;
+    for (int i = 0; i < N; ++i) {
+      for (int k = rp[i]; k < rp[i + 1]; ++k) entl[o++] = make_int2(ci[k], k);
+      for (int e = upp[i]; e < upp[i + 1]; ++e) entl[o++] = upe[e];
+    }
+    entl[o] = make_int2(0, s.nnzb);
+  }
   // device uploads
   std::vector<int4> tet4(T);
   for (int t = 0; t < T; ++t) tet4[t] = make_int4(d->tets[4 * t], d->tets[4 * t + 1], d->tets[4 * t + 2], d->tets[4 * t + 3]);
@@ -778,6 +791,7 @@ static int build_scene(Scene &s, const bal_scene_desc *d) {
       (rc = upload(s, s.row_ptr, rp.data(), N + 1)) || (rc = upload(s, s.col_idx, ci.data(), ci.size())) ||
       (rc = upload(s, s.blk_src_ptr, bsp.data(), bsp.size())) || (rc = upload(s, s.blk_src, bsrc.data(), bsrc.size())) ||
       (rc = upload(s, s.up_ptr, upp.data(), N + 1)) || (rc = upload(s, s.up_ent, upe.data(), upe.size())) ||
+      (s.mixed && (rc = upload(s, s.ent, entl.data(), entl.size()))) ||
       (rc = upload(s, s.sv, s.sv_h.data(), s.sv_h.size())) || (rc = upload(s, s.st, s.st_h.data(), s.st_h.size())) ||
       (rc = upload(s, s.se, s.se_h.data(), s.se_h.size())))
     return rc;
@@ -1042,7 +1056,7 @@ void bal_destroy_scene(bal_scene *h) {
   hipSetDevice(s.dev);
   hipStreamSynchronize(s.stream);
   DBuf *bufs[] = {&s.tets, &s.tc, &s.mass, &s.freev, &s.node_tet_ptr, &s.node_tet_src, &s.row_ptr, &s.col_idx,
-                  &s.blk_src_ptr, &s.blk_src, &s.up_ptr, &s.up_ent, &s.perm_d, &s.stage, &s.sv, &s.st, &s.se, &s.x, &s.v, &s.x_t, &s.v_t, &s.y,
+                  &s.blk_src_ptr, &s.blk_src, &s.up_ptr, &s.up_ent, &s.ent, &s.perm_d, &s.stage, &s.sv, &s.st, &s.se, &s.x, &s.v, &s.x_t, &s.v_t, &s.y,
                   &s.xtrial, &s.dx, &s.tet_e, &s.tet_g, &s.tet_tr, &s.tet_blk, &s.val, &s.Dblk, &s.Dinv, &s.e_nodes,
                   &s.group, &s.grad, &s.grad_b, &s.uni_flag, &s.uni_aug, &s.pair_e, &s.pair_g, &s.pair_tr,
                   &s.pair_blk, &s.cdiag_ptr, &s.cdiag_src, &s.coff_ptr, &s.coff_col, &s.coff_src, &s.ccount,

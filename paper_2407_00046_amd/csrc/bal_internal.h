@@ -79,6 +79,7 @@ struct Scene {
   DBuf hb_lo, hb_hi, hq_lo, hq_hi, h_cnt, h_off, h_key, h_prim, h_bcnt, h_bstart, h_bfill, h_skey, h_sprim,
       h_large, h_nlarge, h_qcnt, h_lcnt, h_qoff, h_out, qoff_pt, out_pt, qoff_ee, out_ee;
   // PCG
+  DBuf ent;  // FP32 storage: per row its lower then transposed entries (operand, block), one dummy at the end
   DBuf r, z, pv, pv2, q, pcg_ctl, warm_ctl, partial, counter, scan_tmp, red_out, flags;
   DBuf node_e, cand_e, mask, mask_off, tau, rhs, psweep;
   DBuf pin;     // pinned host scratch (hipHostMalloc)
