@@ -117,7 +117,8 @@ typedef struct bal_step_stats {
 /* Fills *d with defaults (all pointers NULL, sizes 0). */
 void bal_desc_defaults(bal_scene_desc *d);
 
-/* Builds a scene: validates (finite inputs, indices in range, positive rest
+/* Builds a scene: validates (finite inputs, indices in range, every free
+ * vertex in some tet, else BAL_E_INVALID_ARG; positive rest volumes and x0
  * volumes -> BAL_E_INVERTED, every pair at x0 with d > 0 -> BAL_E_PENETRATION),
  * derives masses, rest shape matrices, the surface and the block-sparse
  * pattern, and allocates device memory.  *out is NULL on error. */

@@ -641,6 +641,9 @@ static int build_scene(Scene &s, const bal_scene_desc *d) {
   }
   s.free_h.assign(N, 0);
   for (int i = 0; i < nb; ++i) s.free_h[i] = d->fixed ? (d->fixed[i] ? 0 : 1) : 1;
+  // a free vertex needs mass: one that belongs to no tet leaves the system singular
+  for (int i = 0; i < nb; ++i)
+    if (s.free_h[i] && !(s.mass_h[i] > 0.0)) return BAL_E_INVALID_ARG;
   // node -> tet incidence (tet*4 + local index), in tet order
   std::vector<int> ntp(N + 1, 0), nts(4 * (size_t)T);
   for (int t = 0; t < T; ++t)
