@@ -812,6 +812,8 @@ static int build_scene(Scene &s, const bal_scene_desc *d) {
       s.pair_tr.grow(64) || s.pair_blk.grow(144 * 8))
     return BAL_E_OOM;
   if (hipHostMalloc(&s.pin.p, 1 << 16) != hipSuccess) return BAL_E_OOM;
+  for (hipEvent_t &e : s.pipe_ev)
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return BAL_E_HIP;
   s.pin.bytes = 1 << 16;
   hipMemsetAsync(s.flags.p, 0, 64, s.stream);
   hipMemsetAsync(s.counter.p, 0, 64, s.stream);
@@ -1078,6 +1080,8 @@ void bal_destroy_scene(bal_scene *h) {
   if (s.pin.p) hipHostFree(s.pin.p);
   for (hipEvent_t e : s.ev_pool) hipEventDestroy(e);
   if (s.cg_exec) hipGraphExecDestroy(s.cg_exec);
+  for (hipEvent_t e : s.pipe_ev)
+    if (e) hipEventDestroy(e);
   if (s.warm_exec) hipGraphExecDestroy(s.warm_exec);
   if (s.own_stream && s.stream) hipStreamDestroy(s.stream);
   delete h;

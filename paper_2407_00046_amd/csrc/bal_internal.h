@@ -87,6 +87,7 @@ struct Scene {
   bool use_graphs = true;
   bool own_stream = false;
   hipGraphExec_t cg_exec = nullptr, warm_exec = nullptr;
+  hipEvent_t pipe_ev[2] = {nullptr, nullptr};  // pipelined PCG chunks: one per control-block copy
   std::vector<uintptr_t> cg_sig, warm_sig;
   // timing
   bool time_kernels = false;

@@ -914,6 +914,9 @@ struct CgCtl {
   int stop;  // raised with the final state: every later launch exits at once
   int pad;
 };
+// pinned-buffer offset of the pipelined chunks' control-block copies
+constexpr size_t kPinPipe = 32768;
+static_assert(kPinPipe + 2 * sizeof(CgCtl) <= 65536, "pinned scratch is 64 KiB");
 struct WarmCtl {
   double rz[kGroups], alpha[kGroups], beta[kGroups], rr[kGroups], ref2[kGroups];
   int active[kGroups];
@@ -1564,6 +1567,41 @@ static int cg_run(Scene &s, const double *rhs, double *xsol, double tol, double 
   sig.insert(sig.end(), {(uintptr_t)p0, (uintptr_t)p1, (uintptr_t)q, (uintptr_t)ctl, (uintptr_t)pq0,
                          (uintptr_t)s.freev.p, (uintptr_t)Dinv, (uintptr_t)xsol, (uintptr_t)r, (uintptr_t)z,
                          (uintptr_t)N});
+  // Graph chunks are pipelined: chunk c + 1 is queued before the host waits
+  // for chunk c's control block, so the stop test leaves the GPU no idle
+  // gap, and after the stop the one queued chunk's launches exit at once.
+  // The control-block copies go to a pinned area of their own (two slots):
+  // the queued chunk's copy may land after this call returns.
+  if (s.use_graphs && !s.time_kernels && (k & 1) == 0 && s.pipe_ev[0] && s.pipe_ev[1]) {
+    if (!graph_current(s.cg_sig, sig, s.cg_exec)) {
+      bool ok = capture_graph(s, s.cg_exec, [&]() {
+        for (int c = 0; c < chunk; ++c) launch_iter(c, nullptr, nullptr);
+      });
+      if (ok) s.cg_sig = sig; else { s.use_graphs = false; s.cg_sig.clear(); }
+    }
+    if (s.use_graphs) {
+      CgCtl *hb = reinterpret_cast<CgCtl *>(static_cast<char *>(s.pin.p) + kPinPipe);
+      auto enqueue = [&](int slot) {
+        if (hipGraphLaunch(s.cg_exec, s.stream) != hipSuccess) return false;
+        ++s.graph_launches;
+        k += chunk;
+        return hipMemcpyAsync(&hb[slot], ctl, sizeof(CgCtl), hipMemcpyDeviceToHost, s.stream) == hipSuccess &&
+               hipEventRecord(s.pipe_ev[slot], s.stream) == hipSuccess;
+      };
+      if (!enqueue(0)) return BAL_E_HIP;
+      for (int c = 0;; ++c) {
+        if (!enqueue((c + 1) & 1)) return BAL_E_HIP;
+        if (hipEventSynchronize(s.pipe_ev[c & 1]) != hipSuccess) return BAL_E_HIP;
+        const CgCtl &hc = hb[c & 1];
+        const CgSlot &sl = hc.slot[hc.slot[0].it >= hc.slot[1].it ? 0 : 1];
+        if (sl.done) {
+          *iters_out = sl.it;
+          *rnorm_out = sl.rnorm;
+          return sl.done == PCG_BREAKDOWN ? BAL_E_NO_CONVERGENCE : BAL_OK;
+        }
+      }
+    }
+  }
   for (;;) {
     bool graphed = false;
     const int first = k;
