@@ -3,10 +3,12 @@
 // reductions and scans.
 //
 // Storage.  The static element part is the strictly lower triangle of a 3x3
-// block CSR over free nodes (plus a transposed index for the upper half),
-// gathered per block from per-tet blocks through a static source list, so
-// assembly and SpMV need no atomics and are bit-reproducible.  Contact blocks stay in per-pair buffers; per Newton
-// iteration each row gets a sorted list of the contact blocks it reads.
+// block CSR over free nodes (plus a transposed index for the upper half; with
+// FP32 blocks also one (operand, block) entry list per row), gathered per
+// block from per-tet blocks through a static source list, so assembly and
+// SpMV need no atomics and are bit-reproducible.  Contact blocks stay in
+// per-pair buffers; per Newton iteration each row gets a sorted list of the
+// contact blocks it reads.
 // Diagonal blocks (mass + elements + contacts) form the dense block
 // diagonal D that also feeds the block-Jacobi preconditioner.
 #include <hip/hip_ext.h>
@@ -825,8 +827,9 @@ double cg_product_bytes(const Scene &s) {
 // The state after iteration k lives in slot k & 1 (the host passes k), so
 // the slot being written is never the slot being read.
 //
-// Warm start (per stiffness group, 64 bins): per-block per-bin partials are
-// reduced by single-block kernels between the vector kernels.
+// Warm start (per stiffness group, 64 bins): per-block per-bin partials;
+// the p.q sums are formed by each update block for the bins it holds, the
+// r.z and r.r sums by one block per bin.
 template <int NB>
 __device__ __forceinline__ int bin_of(const int *grp, int i) {
   if (NB == 1) return 0;
