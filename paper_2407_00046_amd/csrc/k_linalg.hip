@@ -693,6 +693,40 @@ __device__ __forceinline__ void blk_sel(const MT *a, const VT *w, bool tr, bool 
   acc[2] += on ? (tr ? t2 : d2) : (VT)0;
 }
 
+// The row's contact blocks (per-pair block grids read through the row's
+// sorted source list), kC entries per lane per pass: all their indices, then
+// all blocks and operand entries, then the arithmetic, so that a row with
+// many contacts costs a few rounds of memory latency rather than two per
+// entry.  Lanes past the row's end reread a valid entry and drop it.
+constexpr int kC = 4;
+template <typename MT, typename VT, bool MASK, typename F>
+__device__ __forceinline__ void contact_rows(int c0, int c1, int g, const BsrView<MT> &B, const int *__restrict__ grp,
+                                             int gi, const F &v, VT *acc) {
+  for (int c = c0 + g; c < c1; c += kC * kG) {
+    int j[kC];
+    const MT *a[kC];
+    bool on[kC];
+#pragma unroll
+    for (int u = 0; u < kC; ++u) {
+      const int cu = c + u * kG;
+      on[u] = cu < c1;
+      const int ce = on[u] ? cu : c;
+      j[u] = B.cc[ce];
+      a[u] = B.pblk + (size_t)9 * B.cs[ce];
+    }
+    MT blk[kC][9];
+    VT w[kC][3];
+#pragma unroll
+    for (int u = 0; u < kC; ++u) {
+#pragma unroll
+      for (int e = 0; e < 9; ++e) blk[u][e] = a[u][e];
+      v.load(j[u], w[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < kC; ++u) blk_sel<MT, VT>(blk[u], w[u], false, on[u] && (!MASK || grp[j[u]] == gi), acc);
+  }
+}
+
 template <typename MT, typename VT, bool MASK, typename F, typename Pre>
 __device__ __forceinline__ bool spmv_row_pre(int i, int g, const BsrView<MT> &B, const int *__restrict__ grp, F &v,
                                              Pre &&pre, VT *acc, VT *own) {
@@ -742,12 +776,7 @@ __device__ __forceinline__ bool spmv_row_pre(int i, int g, const BsrView<MT> &B,
       if constexpr (kUnifiedWalk<MT>) row_fetch_unified<MT>(t, l0 + u0, nl, nt, B, rb);
       else row_fetch<MT>(i, t, l0, nl, u0, nt, B, rb);
     }
-    for (int c = c0 + g; c < c1; c += kG) {
-      const int j = B.cc[c];
-      VT w0[3];
-      v.load(j, w0);
-      if (!MASK || grp[j] == gi) blk_mv<MT, VT>(B.pblk + (size_t)9 * B.cs[c], w0, acc);
-    }
+    contact_rows<MT, VT, MASK>(c0, c1, g, B, grp, gi, v, acc);
   }
 #pragma unroll
   for (int o = kG / 2; o > 0; o >>= 1)
@@ -1125,11 +1154,7 @@ __global__ __launch_bounds__(kBS) void k_cg_dir_spmv(int N, int k, BsrView<MT> B
       for (int u = 0; u < kU; ++u)
         if (kUnifiedWalk<MT> || rb.on[u]) dir.raw(rb.j[u], zr[u], pr[u]);
     }
-    for (int c = c0 + g; c < c1; c += kG) {
-      VT w0[3];
-      dir.load(B.cc[c], w0);
-      blk_mv<MT, VT>(B.pblk + (size_t)9 * B.cs[c], w0, acc);
-    }
+    contact_rows<MT, VT, false>(c0, c1, g, B, nullptr, 0, dir, acc);
   }
 #pragma unroll
   for (int o = kG / 2; o > 0; o >>= 1)
