@@ -299,22 +299,50 @@ __global__ void k_contact_fill(int n, const int4 *__restrict__ nodes, const int 
   }
 }
 
-// Insertion sort of each node's sources (deterministic order).
-__global__ void k_contact_sort(int N, const int *__restrict__ dptr, int *__restrict__ dsrc,
-                               const int *__restrict__ optr, int *__restrict__ ocol, int *__restrict__ osrc) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  for (int a = dptr[i] + 1; a < dptr[i + 1]; ++a) {
-    int v = dsrc[a], b = a - 1;
-    while (b >= dptr[i] && dsrc[b] > v) { dsrc[b + 1] = dsrc[b]; --b; }
-    dsrc[b + 1] = v;
+// Each node's sources in ascending order (a deterministic order; the sources
+// are distinct).  One wave per node: a list of up to kRankSort entries is
+// staged in LDS and every entry goes to its rank (the number of smaller
+// sources); a longer list is insertion-sorted by one lane.
+constexpr int kRankSort = 256;
+__device__ void rank_sort(int lo, int hi, int *__restrict__ key, int *__restrict__ pay, int *sk, int *sp) {
+  const int m = hi - lo, lane = threadIdx.x;
+  if (m <= 1) return;
+  if (m > kRankSort) {
+    if (lane == 0)
+      for (int a = lo + 1; a < hi; ++a) {
+        const int v = key[a], c = pay ? pay[a] : 0;
+        int b = a - 1;
+        while (b >= lo && key[b] > v) {
+          key[b + 1] = key[b];
+          if (pay) pay[b + 1] = pay[b];
+          --b;
+        }
+        key[b + 1] = v;
+        if (pay) pay[b + 1] = c;
+      }
+    return;
   }
-  for (int a = optr[i] + 1; a < optr[i + 1]; ++a) {
-    int v = osrc[a], c = ocol[a], b = a - 1;
-    while (b >= optr[i] && osrc[b] > v) { osrc[b + 1] = osrc[b]; ocol[b + 1] = ocol[b]; --b; }
-    osrc[b + 1] = v;
-    ocol[b + 1] = c;
+  for (int e = lane; e < m; e += blockDim.x) {
+    sk[e] = key[lo + e];
+    if (pay) sp[e] = pay[lo + e];
   }
+  __syncthreads();
+  for (int e = lane; e < m; e += blockDim.x) {
+    const int v = sk[e];
+    int r = 0;
+    for (int f = 0; f < m; ++f) r += sk[f] < v;
+    key[lo + r] = v;
+    if (pay) pay[lo + r] = sp[e];
+  }
+  __syncthreads();
+}
+
+__global__ void k_contact_sort(const int *__restrict__ dptr, int *__restrict__ dsrc, const int *__restrict__ optr,
+                               int *__restrict__ ocol, int *__restrict__ osrc) {
+  __shared__ int sk[kRankSort], sp[kRankSort];
+  const int i = blockIdx.x;
+  rank_sort(dptr[i], dptr[i + 1], dsrc, nullptr, sk, sp);
+  rank_sort(optr[i], optr[i + 1], osrc, ocol, sk, sp);
 }
 
 int build_contact_lists(Scene &s) {
@@ -340,8 +368,9 @@ int build_contact_lists(Scene &s) {
     hipLaunchKernelGGL(k_contact_fill, dim3(blocks_for(n, kBS)), dim3(kBS), 0, s.stream, n, s.uni.nodes.as<int4>(),
                        s.uni.cs.as<int>(), s.freev.as<uint8_t>(), s.cdiag_ptr.as<int>(), s.coff_ptr.as<int>(), dfill,
                        ofill, s.cdiag_src.as<int>(), s.coff_col.as<int>(), s.coff_src.as<int>());
-    hipLaunchKernelGGL(k_contact_sort, dim3(blocks_for(N, kBS)), dim3(kBS), 0, s.stream, N, s.cdiag_ptr.as<int>(),
-                       s.cdiag_src.as<int>(), s.coff_ptr.as<int>(), s.coff_col.as<int>(), s.coff_src.as<int>());
+    if (N > 0)
+      hipLaunchKernelGGL(k_contact_sort, dim3(N), dim3(64), 0, s.stream, s.cdiag_ptr.as<int>(), s.cdiag_src.as<int>(),
+                         s.coff_ptr.as<int>(), s.coff_col.as<int>(), s.coff_src.as<int>());
   }
   return BAL_OK;
 }
