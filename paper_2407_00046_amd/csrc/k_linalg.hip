@@ -805,7 +805,18 @@ __device__ __forceinline__ bool spmv_row_pre(int i, int g, const BsrView<MT> &B,
       if constexpr (kUnifiedWalk<MT>) row_fetch_unified<MT>(t, l0 + u0, nl, nt, B, rb);
       else row_fetch<MT>(i, t, l0, nl, u0, nt, B, rb);
     }
-    contact_rows<MT, VT, MASK>(c0, c1, g, B, grp, gi, v, acc);
+    if constexpr (kUnifiedWalk<MT>) {
+      contact_rows<MT, VT, MASK>(c0, c1, g, B, grp, gi, v, acc);
+    } else {
+      // FP64 storage: the batched walk changed the plain product's code
+      // enough to cost the 128^3-grid product 392 -> 421 us
+      for (int c = c0 + g; c < c1; c += kG) {
+        const int j = B.cc[c];
+        VT w0[3];
+        v.load(j, w0);
+        if (!MASK || grp[j] == gi) blk_mv<MT, VT>(B.pblk + (size_t)9 * B.cs[c], w0, acc);
+      }
+    }
   }
 #pragma unroll
   for (int o = kG / 2; o > 0; o >>= 1)
