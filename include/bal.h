@@ -58,6 +58,22 @@ enum bal_precision {
                      Newton check and multiplier updates */
 };
 
+/* Activation rule of the CCD step bound (Sec. 5.3, narrow phase).  The roots of
+ * the coplanarity cubic are sought in [-eps, 1+eps] (eps = 1e-12) and clamped
+ * into [0, 1]; a time of coplanarity is activated when the pair's distance
+ * there is below eps + margin. */
+enum bal_ccd_rule {
+  BAL_CCD_PRINTED = 0,  /* margin dhat, as printed; a root at |t| <= eps coincides with the
+                           start frame t0 = 0 of the paper's candidate times and is not a time
+                           of impact (reading: activating it stops every later step of a pair
+                           that an iterate left coplanar inside dhat) */
+  BAL_CCD_HALF_GAP = 1, /* departure (not in the paper): margin d0 / 2 for a pair that starts
+                           closer than dhat (d0 its distance at t = 0), dhat otherwise */
+  BAL_CCD_LITERAL = 2   /* margin dhat and roots at |t| <= eps activated too (the literal
+                           reading; an iterate left on a point-edge coplanarity inside dhat
+                           then bounds every later step at alpha_max = 0) */
+};
+
 typedef struct bal_scene bal_scene;
 
 /* Scene description (read once by bal_create_scene; defaults from bal_desc_defaults). */
@@ -90,6 +106,12 @@ typedef struct bal_scene_desc {
   int32_t precision;           /* bal_precision */
   int32_t warm_start;          /* 1: stiffness-grouped block-Jacobi warm start (Sec. 4.2) */
   int32_t use_al;              /* 1: augmentation set A' (BAL); 0: plain barrier */
+  int32_t ccd_rule;            /* bal_ccd_rule, default BAL_CCD_PRINTED */
+  int32_t sweep_cap;           /* 0 (default): the swept candidate pass halves its sweep only when it
+                                  would exceed its work bound (2^28 direct box tests, the memory
+                                  limit of Sec. 5.2); n > 0 (departure, not in the paper): also while
+                                  some vertex would move more than n mean surface edge lengths.
+                                  alpha_max is then at most the swept fraction of the step */
   int32_t device;              /* HIP device ordinal */
   void *stream;                /* hipStream_t, or NULL for the default stream */
 } bal_scene_desc;

@@ -279,6 +279,74 @@ class Params:
     pair_mode: str = "brute"      # "brute" or "kdtree" (superset for large scenes)
     verbose: bool = False         # print one line per phase of each Newton iteration
     sigma_fixed: float = 0.0      # > 0: sigma held at this value (no sigma^0, no growth)
+    ccd_rule: str = "printed"     # "printed" (Sec. 5.3), "half_gap" (departure) or "literal"; see ccd
+    sweep_cap: float = 0.0        # > 0 (departure): CCD sweep halved while a vertex moves
+                                  # more than sweep_cap mean surface edge lengths
+
+
+# ----------------------------------------------------------------------------
+# Algorithm 1's bookkeeping, as functions of plain arrays.
+# ----------------------------------------------------------------------------
+def rebuild_aug_set(pairs: Pairs, d, min_d, prev_min, st: "ALState", dhat):
+    """Alg. 1 lines 3-6 (reading: "current iterate vs previous iterate").
+
+    Returns (aug, mu, s): A' emptied when min d exceeds 1e-2 dhat; rebuilt as
+    the pairs of `pairs` with d < 1e-2 dhat when min d decreased or A' is
+    empty (a pair kept across a rebuild keeps its mu and s, a new one starts
+    at 0; reading); otherwise unchanged.
+    """
+    if min_d > 1e-2 * dhat:
+        return Pairs.empty(), np.zeros(0), np.zeros(0)
+    if not (min_d < prev_min or len(st.aug) == 0):
+        return st.aug, st.mu, st.s
+    new = pairs.take(np.nonzero(np.asarray(d) < 1e-2 * dhat)[0])
+    mu = np.zeros(len(new))
+    sl = np.zeros(len(new))
+    if len(st.aug):
+        pos = {k: i for i, k in enumerate(st.aug.keys())}
+        for i, k in enumerate(new.keys()):
+            j = pos.get(k)
+            if j is not None:
+                mu[i], sl[i] = st.mu[j], st.s[j]
+    return new, mu, sl
+
+
+def slack_update(mu, d, sigma, dhat):
+    """Slack of each A' pair: the minimiser over s >= 0 of
+    mu (dhat + s - d) + sigma/2 (dhat + s - d)^2 (eq. problem-s), in closed form."""
+    return np.maximum(-np.asarray(mu) / sigma - dhat + np.asarray(d), 0.0)
+
+
+def dual_update(mu, d, sigma, dhat):
+    """Alg. 1 lines 12-14 for every pair of A' at distances d (at x^{l+1}):
+    first s_i, then mu_i += sigma b(d_i, dhat + s_i) with the new s_i.
+    Returns (mu_new, s_new)."""
+    sl = slack_update(mu, d, sigma, dhat)
+    return np.asarray(mu) + sigma * barrier_np(d, dhat + sl), sl
+
+
+def sigma_update(sigma, sigma0, min_d_new, dhat):
+    """Alg. 1 lines 15-17: sigma <- max(1.2 sigma, 100 sigma^0) when min d < 1e-2 dhat."""
+    if min_d_new < 1e-2 * dhat:
+        return max(1.2 * sigma, 100.0 * sigma0)
+    return sigma
+
+
+def line_search(alpha_max, L0, trial, min_alpha=1e-9):
+    """Backtracking from alpha_max (Sec. 5.2; reading: plain non-increase).
+
+    trial(alpha) -> (L, feasible, within_capacity).  alpha halves until
+    L <= L0 at a feasible trial point (every J > 0 and d > 0) whose active
+    count is within the memory limit; below min_alpha the search fails and
+    returns 0.
+    """
+    alpha = alpha_max
+    while alpha >= min_alpha:
+        L, ok, cap = trial(alpha)
+        if ok and cap and L <= L0:
+            return alpha
+        alpha *= 0.5
+    return 0.0
 
 
 class OracleScene:
@@ -319,12 +387,10 @@ class OracleScene:
         self.v = np.concatenate([np.asarray(sc["v0"], dtype=np.float64), np.zeros((m, 3))])
         self.v[~self.free] = 0.0
         self._surface(T, np.asarray(sc["obs_tris"], dtype=np.int64).reshape(-1, 3))
-        # longest CCD sweep of one vertex per pass: 16 mean body surface edge
-        # lengths (at least 4 dhat each); longer steps are halved first
-        # (reading of the memory-limited step halving, Sec. 5.2)
+        # unit of the optional sweep cap: the mean body surface edge length at rest (at least 4 dhat)
         be = self.s_edges[(self.s_edges < n).all(1)]
         mean_edge = float(np.linalg.norm(X[be[:, 0]] - X[be[:, 1]], axis=1).mean()) if len(be) else 1.0
-        self.sweep_len = 16.0 * max(mean_edge, 4.0 * self.dhat)
+        self.mean_edge = max(mean_edge, 4.0 * self.dhat)
         self._t_dminv = torch.tensor(self.Dm_inv, dtype=DT)
         self._t_vol = torch.tensor(self.vol, dtype=DT)
         self._set_material()
@@ -719,21 +785,21 @@ class OracleScene:
 
         Per pair: roots of the coplanarity cubic in [-eps, 1+eps] (clamped to
         [0, 1]) are visited in order t1 <= t2 <= t3 with t0 = 0; the first
-        root whose distance d_TOC < eps + dhat is activated, tau = t_{i+1}
-        (reading: for a pair already closer than dhat at the start of the
-        step, the margin is half its current distance instead of dhat, since
-        with dhat every near miss of two primitives sliding in contact would
-        stop the step at the coplanar time);
+        root whose distance d_TOC < eps + dhat is activated, tau = t_{i+1};
         for point-triangle / edge-edge interior cases tau shrinks by 0.9
         while sign sd(tau) != sign sd((t_i + tau) / 2) (reading of the
         reference-frame rule; |sd| <= eps counts as sign 0, so a tau sitting
         on the coplanarity root always backs off); point-point / point-edge
-        cases keep tau.
-        Edge pairs parallel at both ends of the step are skipped (reading: a
-        parallel edge pair is coplanar for every t), and roots at t <= eps
-        are not activated (reading: they describe the feasible start of the
-        step; activating them would pin alpha_max at 0 once an iterate lands
-        on a point-edge time of coplanarity).
+        cases keep tau.  Edge pairs parallel at both ends of the step are
+        skipped (reading: a parallel edge pair is coplanar for every t).
+        A root at |t| <= eps coincides with the start frame t0 = 0 of the
+        candidate times and is not a time of impact (reading: activating it
+        bounds every later step of a pair that an iterate left coplanar
+        inside dhat at alpha_max = 0).
+
+        Other rules: "literal" activates roots at |t| <= eps as well;
+        "half_gap" (a departure from the printed rule) takes half the pair's
+        current distance as the margin when the pair starts closer than dhat.
         """
         K = len(pairs)
         tau = np.ones(K)
@@ -762,17 +828,22 @@ class OracleScene:
             skip = np.zeros(K, bool)
             skip[ee] = par(X0[ee]) & par(X1[ee])
             roots[skip] = np.nan
-        # activation margin: dhat for pairs approaching from outside the barrier
-        # zone, half the current distance for pairs already inside it (reading)
-        q_start, _ = classify(pairs.kind, X0)
-        d_start = np.sqrt(q_start)
-        margin = np.where(d_start < self.dhat, 0.5 * d_start, self.dhat)
+        rule = self.p.ccd_rule
+        if rule not in ("printed", "half_gap", "literal"):
+            raise ValueError(rule)
+        margin = np.full(K, self.dhat)
+        if rule == "half_gap":
+            q_start, _ = classify(pairs.kind, X0)
+            d_start = np.sqrt(q_start)
+            margin = np.where(d_start < self.dhat, 0.5 * d_start, self.dhat)
         done = np.zeros(K, dtype=bool)
         t_prev = np.zeros(K)
         for k in range(3):
             r = roots[:, k]
-            # a root at t <= eps describes the (feasible) start of the step: not activated (reading)
-            cand = np.isfinite(r) & ~done & (r > CCD_EPS)
+            cand = np.isfinite(r) & ~done
+            if rule != "literal":
+                # a root at |t| <= eps is the start frame t0 = 0 itself (reading)
+                cand &= r > CCD_EPS
             if not cand.any():
                 continue
             idx = np.nonzero(cand)[0]
@@ -851,20 +922,7 @@ class OracleScene:
             active = d < dh
             # A' update (Alg. 1, lines 3-6; reading: current vs previous iterate)
             if p.use_al:
-                if min_d > 1e-2 * dh:
-                    st.aug, st.mu, st.s = Pairs.empty(), np.zeros(0), np.zeros(0)
-                elif min_d < prev_min or len(st.aug) == 0:
-                    new = pairs.take(np.nonzero(active & (d < 1e-2 * dh))[0])
-                    nk, ok = new.keys(), st.aug.keys()
-                    mu = np.zeros(len(new))
-                    s = np.zeros(len(new))
-                    if len(st.aug):
-                        pos = {k: i for i, k in enumerate(ok)}
-                        for i, k in enumerate(nk):
-                            j = pos.get(k)
-                            if j is not None:
-                                mu[i], s[i] = st.mu[j], st.s[j]
-                    st.aug, st.mu, st.s = new, mu, s
+                st.aug, st.mu, st.s = rebuild_aug_set(pairs, d, min_d, prev_min, st, dh)
             prev_min = min_d
             if st.sigma is None and active.any():
                 s0 = self.sigma0(x, y, pairs.take(np.nonzero(active)[0]), st)
@@ -884,26 +942,24 @@ class OracleScene:
             P = np.zeros_like(x)
             P[self.free_idx] = dx.reshape(-1, 3)
             sw = 1.0
-            pmax = float(np.sqrt((P * P).sum(1).max())) if len(P) else 0.0
-            while sw * pmax > self.sweep_len and sw > 1e-30:
-                sw *= 0.5
+            if p.sweep_cap > 0.0:
+                pmax = float(np.sqrt((P * P).sum(1).max())) if len(P) else 0.0
+                while sw * pmax > p.sweep_cap * self.mean_edge and sw > 1e-30:
+                    sw *= 0.5
             swept = self.candidate_pairs(x, disp=sw * P)
             amax = sw * self.ccd(x, sw * P, swept)
             self._log(f"iteration {it}: CCD over {len(swept)} pairs, alpha_max = {amax:.3e}", t0)
-            alpha = amax
-            while True:
-                xn = x + alpha * P
-                ok = True
+
+            def trial(a):
+                xa = x + a * P
+                cap = True
                 if p.max_contacts < (1 << 40):
-                    dn, _ = self.distances(xn, swept)
-                    ok = int((dn < dh).sum()) <= p.max_contacts
-                if ok and self.lagrangian(xn, y, swept, st) <= L0:
-                    break
-                alpha *= 0.5
-                if alpha < p.min_alpha:
-                    alpha = 0.0
-                    xn = x.copy()
-                    break
+                    da, _ = self.distances(xa, swept)
+                    cap = int((da < dh).sum()) <= p.max_contacts
+                La = self.lagrangian(xa, y, swept, st)
+                return La, bool(np.isfinite(La)), cap
+            alpha = line_search(amax, L0, trial, p.min_alpha)
+            xn = x + alpha * P
             if trace is not None:
                 trace.append(dict(it=it, n_active=int(active.sum()), n_aug=len(st.aug),
                                   sigma=st.sigma, min_d=min_d, alpha_max=amax, alpha=alpha, enorm=en))
@@ -919,10 +975,9 @@ class OracleScene:
             dn, _ = self.distances(xn, swept)
             if len(st.aug):
                 da, _ = self.distances(xn, st.aug)
-                st.s = np.maximum(-st.mu / st.sigma - dh + da, 0.0)
-                st.mu = st.mu + st.sigma * barrier_np(da, dh + st.s)
-            if dn.size and dn.min() < 1e-2 * dh and st.sigma is not None and not p.sigma_fixed > 0.0:
-                st.sigma = max(1.2 * st.sigma, 100.0 * st.sigma0)
+                st.mu, st.s = dual_update(st.mu, da, st.sigma, dh)
+            if dn.size and st.sigma is not None and not p.sigma_fixed > 0.0:
+                st.sigma = sigma_update(st.sigma, st.sigma0, float(dn.min()), dh)
             x = xn
         self.x = x
         self.v = (x - x_t) / self.h
@@ -971,6 +1026,7 @@ class OracleScene:
 
 __all__ = [
     "OracleScene", "Params", "ALState", "Pairs", "classify", "classify_pt", "classify_ee",
+    "rebuild_aug_set", "slack_update", "dual_update", "sigma_update", "line_search",
     "point_segment_sq", "q_case_torch", "barrier_np", "barrier_torch", "lame", "nh_density_torch",
     "project_psd", "CASE_NODES", "CASE_KIND", "CCD_EPS", "PARALLEL_EPS",
 ]

@@ -24,6 +24,8 @@ _lib = C.CDLL(LIB_PATH)
 BAL_OK, BAL_E_INVALID_ARG, BAL_E_OOM, BAL_E_HIP = 0, -1, -2, -3
 BAL_E_PENETRATION, BAL_E_INVERTED, BAL_E_CAPACITY, BAL_E_NO_CONVERGENCE, BAL_E_STATE = -4, -5, -6, -7, -8
 BAL_FP64, BAL_MIXED = 0, 1
+BAL_CCD_PRINTED, BAL_CCD_HALF_GAP, BAL_CCD_LITERAL = 0, 1, 2
+CCD_RULES = {"printed": BAL_CCD_PRINTED, "half_gap": BAL_CCD_HALF_GAP, "literal": BAL_CCD_LITERAL}
 
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int32)
@@ -40,7 +42,8 @@ class bal_scene_desc(C.Structure):
         ("newton_rtol", C.c_double), ("pcg_rtol", C.c_double), ("sigma_fixed", C.c_double),
         ("max_newton", C.c_int32), ("max_pcg", C.c_int32), ("pcg_stall_window", C.c_int32),
         ("max_contacts", C.c_int32), ("warm_iters", C.c_int32), ("precision", C.c_int32),
-        ("warm_start", C.c_int32), ("use_al", C.c_int32), ("device", C.c_int32), ("stream", C.c_void_p),
+        ("warm_start", C.c_int32), ("use_al", C.c_int32), ("ccd_rule", C.c_int32), ("sweep_cap", C.c_int32),
+        ("device", C.c_int32), ("stream", C.c_void_p),
     ]
 
 
@@ -118,8 +121,9 @@ class Scene:
 
     `sc` is a scene dict (see scenes/); keyword arguments override the
     bal_scene_desc defaults (precision "fp64" or "mixed", warm_start, use_al,
-    newton_rtol, pcg_rtol, max_newton, max_pcg, pcg_stall_window,
-    max_contacts, warm_iters, device, stream).
+    ccd_rule "printed", "half_gap" or "literal", sweep_cap, newton_rtol, pcg_rtol,
+    max_newton, max_pcg, pcg_stall_window, max_contacts, warm_iters,
+    sigma_fixed, device, stream).
     """
 
     def __init__(self, sc, precision="fp64", **kw):
@@ -158,6 +162,8 @@ class Scene:
                 d.stream = C.c_void_p(v)
             elif k in ("warm_start", "use_al"):
                 setattr(d, k, int(bool(v)))
+            elif k == "ccd_rule":
+                d.ccd_rule = CCD_RULES[v] if isinstance(v, str) else int(v)
             else:
                 setattr(d, k, v)
         self.desc = d

@@ -117,16 +117,17 @@ __global__ void k_scale(const double *__restrict__ a, double f, double *__restri
   if (i < n) b[i] = f * a[i];
 }
 
-// Largest sweep s (a power of 1/2, at most 1) for which no vertex moves more
-// than kSweepCells hash cells along s p: the swept candidate boxes then stay
-// on the hash's cell path (memory-limited halving of the step, Sec. 5.2).
-constexpr double kSweepCells = 16.0;
+// With sweep_cap = n > 0 (not in the paper): the largest sweep s (a power of
+// 1/2, at most 1) for which no vertex moves more than n mean surface edge
+// lengths along s p.  Without it the sweep starts at the whole step and
+// halves only when the candidate pass exceeds its work bound.
 static double sweep_limit(Scene &s, const double *p) {
+  if (s.desc.sweep_cap <= 0) return 1.0;
   if (s.tau.grow((size_t)(s.N + 1) * 8)) return 1.0;
   hipLaunchKernelGGL(k_neg_norm2, dim3(blocks_for(s.N, 256)), dim3(256), 0, s.stream, p, s.tau.as<double>(), s.N);
   double pmax = std::sqrt(std::max(0.0, -reduce_min(s, s.tau.as<double>(), s.N)));
   double sw = 1.0;
-  while (sw * pmax > kSweepCells * s.cell && sw > 1e-30) sw *= 0.5;
+  while (sw * pmax > (double)s.desc.sweep_cap * s.cell && sw > 1e-30) sw *= 0.5;
   return sw;
 }
 
@@ -863,6 +864,7 @@ static int validate_desc(const bal_scene_desc *d) {
   for (int k = 0; k < 3 * d->n_obs_tris; ++k)
     if (d->obs_tris[k] < 0 || d->obs_tris[k] >= d->n_obs_verts) return BAL_E_INVALID_ARG;
   if (d->max_newton <= 0 || d->max_pcg <= 0 || d->precision < 0 || d->precision > 1) return BAL_E_INVALID_ARG;
+  if (d->ccd_rule < BAL_CCD_PRINTED || d->ccd_rule > BAL_CCD_LITERAL || d->sweep_cap < 0) return BAL_E_INVALID_ARG;
   return BAL_OK;
 }
 

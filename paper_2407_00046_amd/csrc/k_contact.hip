@@ -351,8 +351,20 @@ __device__ __forceinline__ double signed_dist(int kind, const v3 *X) {
 // Sign with a dead zone of the CCD epsilon: |sd| <= eps counts as touching (sign 0).
 __device__ __forceinline__ double sgn(double v) { return v > kCcdEps ? 1.0 : (v < -kCcdEps ? -1.0 : 0.0); }
 
+// Conservative time of impact of one candidate pair along x + t p, t in [0, 1]
+// (Sec. 5.3 narrow phase).  The roots of the coplanarity cubic in
+// [-eps, 1+eps] (clamped into [0, 1]) are the times of coplanarity t1 <= t2 <=
+// t3 after t0 = 0; the first whose distance there is below eps + margin is
+// activated, tau = that time.  For a point-triangle or edge-edge interior
+// case tau shrinks by 0.9 while the signed distance at tau and at the
+// reference time (t_prev + tau) / 2 differ in sign (|sd| <= eps counts as
+// sign 0, so tau never rests on the coplanarity itself); point-point and
+// point-edge cases keep tau.  Rules (bal_ccd_rule): printed, margin = dhat
+// and a root at |t| <= eps is the start frame t0 = 0, not a time of impact;
+// half-gap (not in the paper), margin = d0 / 2 for a pair that starts closer
+// than dhat; literal, margin = dhat with roots at |t| <= eps activated.
 __global__ void k_ccd(int n, const int *__restrict__ kind, const int4 *__restrict__ nodes, const double *__restrict__ x,
-                      const double *__restrict__ p, double dhat, double *__restrict__ tau) {
+                      const double *__restrict__ p, double dhat, int rule, double *__restrict__ tau) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   int4 nd = nodes[i];
@@ -382,16 +394,16 @@ __global__ void k_ccd(int n, const int *__restrict__ kind, const int4 *__restric
   double c3 = dot(u1, cross(v1, w1));
   double roots[3];
   int nr = cubic_roots(c3, c2, c1, c0, -kCcdEps, 1.0 + kCcdEps, roots);
-  // activation margin: dhat for a pair approaching from outside the barrier
-  // zone; half the current distance for a pair already inside it (a margin of
-  // dhat there would stop every near miss of two primitives sliding in contact)
-  int cs0;
-  const double d0 = sqrt(pair_classify(kd, X0, &cs0));
-  const double margin = d0 < dhat ? 0.5 * d0 : dhat;
+  double margin = dhat;
+  if (rule == BAL_CCD_HALF_GAP) {
+    int cs0;
+    const double d0 = sqrt(pair_classify(kd, X0, &cs0));
+    if (d0 < dhat) margin = 0.5 * d0;
+  }
   double tprev = 0.0;
   for (int k = 0; k < nr; ++k) {
-    if (roots[k] <= kCcdEps) continue;  // coplanar at the (feasible) start of the step
-    double tk = fmin(roots[k], 1.0);
+    if (rule != BAL_CCD_LITERAL && roots[k] <= kCcdEps) continue;
+    double tk = fmin(fmax(roots[k], 0.0), 1.0);
     v3 Xt[4];
 #pragma unroll
     for (int m = 0; m < 4; ++m) Xt[m] = X0[m] + tk * P[m];
@@ -422,7 +434,7 @@ __global__ void k_ccd(int n, const int *__restrict__ kind, const int4 *__restric
 void launch_ccd(Scene &s, const PairList &pl, const double *x, const double *p, double *tau) {
   if (pl.n == 0) return;
   hipLaunchKernelGGL(k_ccd, dim3(blocks_for(pl.n, 128)), dim3(128), 0, s.stream, pl.n, pl.kind.as<int>(),
-                     pl.nodes.as<int4>(), x, p, s.desc.dhat, tau);
+                     pl.nodes.as<int4>(), x, p, s.desc.dhat, s.desc.ccd_rule, tau);
 }
 
 }  // namespace bal
