@@ -6,16 +6,30 @@ projection, assembly, warm start, PCG, CCD, line search, dual updates).
 
 Workload: 8 randomly rotated cubes of 16^3 cells x 5 tets (163,840 tets,
 39,304 vertices) stacked with 5 mm gaps above a ground plane, E = 1e6 Pa,
-nu = 0.45, h = 1/30 s, dhat = 1e-3 m, Newton and PCG tolerances 1e-4.
-The headline value is seconds per time step in mixed precision over the
+nu = 0.45, h = 1/30 s, dhat = 1e-3 m, Newton and PCG tolerances 1e-4, the
 workload's 10 steps (the cubes fall, collide and stack: the early steps are
 contact-light, the later ones carry thousands of active pairs and most of
-the Newton and PCG iterations); the FP64 form runs the same steps for
-comparison.  The roofline object covers the
-dominant kernel (the PCG block SpMV), timed with HIP events on the scene's
-stream inside the timed steps.  The CPU baseline times the FP64 oracle on a
-bounded sample of the same workload (its first Newton iteration) and
-scales it by the GPU's Newton iterations per step.
+the Newton and PCG iterations).  K timed steps walk those 10 steps in order
+and start again from the initial state after the tenth.
+
+The headline value is seconds per time step in FP64 (the paper's precision).
+Mixed precision runs each of the same steps from the FP64 trajectory's state
+at its start, so both precisions are timed on identical states, and the
+one-step position error of mixed against FP64 is reported per step.  The
+roofline object covers the dominant kernel (the FP64 PCG block SpMV), timed
+with HIP events on the scene's stream over a replay of the timed steps.  The
+CPU baseline times the FP64 oracle on one contact-heavy Newton iteration of
+two of the cubes (face to face, 0.5 mm apart: inside dhat) and scales it by
+4 and by the GPU's Newton iterations per step.
+
+Other modes (one JSON line each):
+  --large       one frame of the large chain net (1,762,560 tets) in FP64 and mixed
+  --ablations   the stacked boxes with warm_start = 0 and with use_al = 0 (FP64)
+  --traffic boxes|grid
+                the workload for PMC traffic counters (run under rocprofv3 --pmc):
+                a 512 MiB streaming copy to calibrate the counters, then PCG
+                products on the stacked boxes' matrix after one step (boxes) or
+                block SpMVs on the 128^3-cell grid (grid)
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -33,6 +47,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+METRIC = "s/timestep & PCG iters/s, mixed vs FP64 at 1e-4 tol; BSR SpMV HBM GB/s"
+TOL = dict(newton_rtol=1e-4, pcg_rtol=1e-4)
 
 
 def recorded_traffic(kernel):
@@ -58,81 +74,113 @@ def recorded_traffic(kernel):
     return None
 
 
-def run_precision(sc, precision, steps, warmup, stream, replay=True):
-    """Times `steps` steps after `warmup` steps (PCG replayed as HIP graphs),
-    then, with `replay`, replays the same steps from the same state with
-    kernel timing on (every PCG SpMV bracketed by HIP events on the scene's
-    stream) for the SpMV roofline."""
-    import torch
-    from paper_2407_00046_amd import Scene
-    g = Scene(sc, precision=precision, newton_rtol=1e-4, pcg_rtol=1e-4, device=0, stream=stream)
-    for _ in range(warmup):
-        g.step(allow=(0, -7))
-    x_w, v_w = g.get_state()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    stats = []
-    for _ in range(steps):
-        stats.append(g.step(allow=(0, -7)))
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    x_end, _ = g.get_state()
-    print(f"[bench] {precision}: {steps} steps in {wall:.1f} s", flush=True)
-    timed = []
-    if replay:
-        g.set_state(x_w, v_w)
-        g.set_kernel_timing(True)
-        timed = [g.step(allow=(0, -7)) for _ in range(steps)]
-        g.set_kernel_timing(False)
-    newton = sum(s["newton_iters"] for s in stats)
+def summarize(stats, wall):
+    n = len(stats)
     pcg = sum(s["pcg_iters"] for s in stats)
     warm = sum(s["warm_iters"] for s in stats)
     sec_pcg = sum(s["sec_pcg"] for s in stats)
+    return dict(
+        s_per_step=wall / n,
+        newton_iters_per_step=sum(s["newton_iters"] for s in stats) / n,
+        pcg_iters_per_step=pcg / n,
+        warm_iters_per_step=warm / n,
+        pcg_iters_per_s=(pcg + warm) / sec_pcg if sec_pcg > 0 else None,
+        sec_pcg_per_step=sec_pcg / n,
+        sec_hessian_per_step=sum(s["sec_hessian"] for s in stats) / n,
+        sec_ccd_per_step=sum(s["sec_ccd"] for s in stats) / n,
+        sec_collision_per_step=sum(s["sec_collision"] for s in stats) / n,
+        sec_linesearch_per_step=sum(s["sec_linesearch"] for s in stats) / n,
+        n_active_max=max(s["n_active_max"] for s in stats),
+        n_aug_max=max(s["n_aug_max"] for s in stats),
+        converged_steps=sum(s["converged"] for s in stats),
+        steps=n,
+    )
+
+
+def run_fp64(sc, steps, warmup, stream, **kw):
+    """W untimed steps, then K timed steps walking the workload's steps from
+    its initial state; then a replay of the workload's steps with kernel timing
+    that also records the state at the start of each step (the replay takes
+    bitwise the same steps: every reduction sums in a fixed order)."""
+    import torch
+    from paper_2407_00046_amd import Scene
+    n_wl = int(sc["n_steps"])
+    g = Scene(sc, precision="fp64", device=0, stream=stream, **TOL, **kw)
+    x0, v0 = g.get_state()
+    for k in range(warmup):
+        if k and k % n_wl == 0:
+            g.set_state(x0, v0)
+        g.step(allow=(0, -7))
+    g.set_state(x0, v0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for k in range(steps):
+        if k and k % n_wl == 0:
+            g.set_state(x0, v0)
+        stats.append(g.step(allow=(0, -7)))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    print(f"[bench] fp64: {steps} steps in {wall:.1f} s", flush=True)
+    g.set_state(x0, v0)
+    g.set_kernel_timing(True)
+    states, timed = [(x0, v0)], []
+    for k in range(min(steps, n_wl)):
+        timed.append(g.step(allow=(0, -7)))
+        states.append(g.get_state())
+    g.set_kernel_timing(False)
+    g.close()
+    out = summarize(stats, wall)
+    out["per_step"] = [dict(status=s["status"], newton=s["newton_iters"], pcg=s["pcg_iters"], warm=s["warm_iters"],
+                            active=s["n_active_max"], sec=round(s["sec_total"], 4)) for s in stats[:n_wl]]
     spmv_ms = sum(s["spmv_ms"] for s in timed)
     spmv_n = sum(s["spmv_launches"] for s in timed)
-    out = dict(
-        s_per_step=wall / steps,
-        newton_iters_per_step=newton / steps,
-        pcg_iters_per_step=pcg / steps,
-        warm_iters_per_step=warm / steps,
-        pcg_iters_per_s=(pcg + warm) / sec_pcg if sec_pcg > 0 else None,
-        sec_pcg_per_step=sec_pcg / steps,
-        sec_hessian_per_step=sum(s["sec_hessian"] for s in stats) / steps,
-        sec_ccd_per_step=sum(s["sec_ccd"] for s in stats) / steps,
-        sec_collision_per_step=sum(s["sec_collision"] for s in stats) / steps,
-        sec_linesearch_per_step=sum(s["sec_linesearch"] for s in stats) / steps,
-        graph_launches_per_step=sum(s["graph_launches"] for s in stats) / steps,
-        n_active_max=max(s["n_active_max"] for s in stats),
-        converged_steps=sum(s["converged"] for s in stats),
-        timed_replay_same_iters=([s["pcg_iters"] for s in timed] == [s["pcg_iters"] for s in stats]) if replay
-        else None,
-        spmv_launches=spmv_n,
-        spmv_ms_avg=spmv_ms / spmv_n if spmv_n > 0 else None,
-        spmv_bytes=(timed or stats)[-1]["spmv_bytes"],
-    )
-    if spmv_n > 0 and spmv_ms > 0:
-        out["spmv_gbs"] = out["spmv_bytes"] / (out["spmv_ms_avg"] * 1e-3) / 1e9
-    g.close()
-    return out, x_end
+    out["replay_same_iters"] = [s["pcg_iters"] for s in timed] == [s["pcg_iters"] for s in stats[:len(timed)]]
+    out["spmv_launches"] = spmv_n
+    out["spmv_ms_avg"] = spmv_ms / spmv_n if spmv_n else None
+    # algorithmic bytes of each step's product launches, weighted by their launch counts
+    w_bytes = sum(s["spmv_bytes"] * s["spmv_launches"] for s in timed)
+    out["spmv_bytes_avg"] = w_bytes / spmv_n if spmv_n else None
+    if spmv_n and spmv_ms > 0:
+        out["spmv_gbs"] = w_bytes / (spmv_ms * 1e-3) / 1e9
+    return out, states
 
 
-def copy_peak_gbs(stream, mib=2048, reps=20):
-    """Streaming-copy bandwidth (read + write bytes) of a device-to-device copy."""
+def run_mixed_from(sc, states, steps, stream, **kw):
+    """Mixed-precision steps, each started from the FP64 trajectory's state at
+    the start of that step: the same K steps as the FP64 run, on identical
+    states; eps_x[k] = max_v |x_mixed - x_fp64| / (scene diagonal) after step k."""
     import torch
-    n = mib * (1 << 20) // 4
-    a = torch.ones(n, dtype=torch.float32, device="cuda")
-    b = torch.empty_like(a)
-    b.copy_(a)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        b.copy_(a)
-    e1.record()
-    e1.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    del a, b
-    torch.cuda.empty_cache()
-    return 2.0 * n * 4 / (ms * 1e-3) / 1e9
+    from paper_2407_00046_amd import Scene
+    n_wl = len(states) - 1
+    L = float(np.linalg.norm(sc["x0"].max(0) - sc["x0"].min(0)))
+    g = Scene(sc, precision="mixed", device=0, stream=stream, **TOL, **kw)
+    stats, eps, wall = [], [], 0.0
+    for k in range(steps):
+        x, v = states[k % n_wl]
+        g.set_state(x, v)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stats.append(g.step(allow=(0, -7)))
+        torch.cuda.synchronize()
+        wall += time.perf_counter() - t0
+        if k < n_wl:
+            xm, _ = g.get_state()
+            eps.append(float(np.linalg.norm(xm - states[k + 1][0], axis=1).max() / L))
+    g.close()
+    print(f"[bench] mixed: {steps} steps in {wall:.1f} s (each from the FP64 state)", flush=True)
+    out = summarize(stats, wall)
+    out["per_step"] = [dict(status=s["status"], newton=s["newton_iters"], pcg=s["pcg_iters"], warm=s["warm_iters"],
+                            active=s["n_active_max"], sec=round(s["sec_total"], 4)) for s in stats[:n_wl]]
+    out["eps_x_vs_fp64_per_step"] = eps
+    out["eps_x_vs_fp64_max"] = max(eps) if eps else None
+    return out
+
+
+def stream_peak():
+    from paper_2407_00046_amd import bal
+    rd, cp = bal.stream_benchmark(0, 2 << 30, 20)
+    return dict(read_gbs=rd, copy_gbs=cp, kernel="k_stream_read / k_stream_copy (2 GiB)")
 
 
 def spmv_r1(stream, n=128, reps=50):
@@ -156,27 +204,142 @@ def spmv_r1(stream, n=128, reps=50):
     return out
 
 
-def cpu_baseline(sc, gpu_newton_per_step):
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(gpu_newton_per_step, threads_one=True):
+    """The FP64 oracle on one contact-heavy Newton iteration of a quarter of
+    the workload: 2 of its 8 cubes, axis-aligned and face to face 0.5 mm apart
+    above the ground (about 14,500 pairs inside dhat from the first iteration,
+    as many as the workload's contact-heavy steps carry), timed with every host
+    thread and with one; scaled by 4 for the workload's 8 cubes and by the
+    GPU's Newton iterations per step."""
     import torch
+    import scenes
     from oracle import OracleScene, Params
-    o = OracleScene(sc, Params(newton_rtol=1e-4, max_newton=1, pair_mode="kdtree", verbose=True))
-    t0 = time.perf_counter()
-    o.step()
-    sec = time.perf_counter() - t0
-    return dict(value=sec * gpu_newton_per_step, unit="s/step", cores=torch.get_num_threads(), kind="oracle",
-                sample=f"first Newton iteration of step 1 of the same workload ({sec:.1f} s), "
-                       f"scaled by the GPU's {gpu_newton_per_step:.1f} Newton iterations per step")
+    sc = scenes.stacked_boxes(n_cubes=2, cells=16, seed=0, gap=5e-4, rotate=False)
+    scale = 4.0
+
+    def one_iteration():
+        o = OracleScene(sc, Params(newton_rtol=1e-4, max_newton=1, pair_mode="kdtree", verbose=True))
+        t0 = time.perf_counter()
+        tr = []
+        o.step(trace=tr)
+        return time.perf_counter() - t0, tr[0]["n_active"]
+
+    threads = torch.get_num_threads()
+    sec, nact = one_iteration()
+    sec1 = None
+    if threads_one:
+        torch.set_num_threads(1)
+        try:
+            sec1, _ = one_iteration()
+        finally:
+            torch.set_num_threads(threads)
+    per_iter = scale * sec
+    return dict(value=per_iter * gpu_newton_per_step, unit="s/step", cores=threads, kind="oracle",
+                sample=(f"one Newton iteration of 2 of the 8 cubes face to face 0.5 mm apart ({nact} pairs inside "
+                        f"dhat): {sec:.1f} s on {threads} threads, x4 for the 8 cubes, x the GPU's "
+                        f"{gpu_newton_per_step:.1f} FP64 Newton iterations per step"),
+                cpu_model=cpu_model(), sec_per_newton_iter=per_iter,
+                sec_per_newton_iter_1thread=scale * sec1 if sec1 else None,
+                value_1thread=scale * sec1 * gpu_newton_per_step if sec1 else None)
+
+
+def roofline_of(run, kernel):
+    ach = run.get("spmv_gbs")
+    if not ach:
+        return None
+    rec = recorded_traffic(kernel)
+    roof = dict(bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
+                traffic=rec["bytes_per_launch"] if rec else None, kernel=kernel,
+                bytes_per_launch=run["spmv_bytes_avg"], avg_launch_ms=run["spmv_ms_avg"])
+    if rec:
+        roof["traffic_note"] = (f"PMC on the same kernel source: {rec['bytes_per_launch']} B per launch vs "
+                                f"{rec['algorithmic_bytes_probe']} B algorithmic on the probe's matrix")
+    return roof
+
+
+def mode_traffic(which, stream):
+    """Counter workload: a calibration copy of 512 MiB, then the products."""
+    import scenes
+    from paper_2407_00046_amd import Scene, bal
+    bal.stream_benchmark(0, 512 << 20, 3)
+    print("[traffic] calibration: 3 reads and 3 copies of 512 MiB (k_stream_read, k_stream_copy)", flush=True)
+    if which == "grid":
+        sc = scenes.spmv_grid(128)
+        for prec in ("mixed", "fp64"):
+            g = Scene(sc, precision=prec, device=0, stream=stream)
+            g.linearize(np.asarray(sc["x0"]), sigma=0.0)
+            ms, by = g.spmv_benchmark(reps=5)
+            g.close()
+            print(f"[traffic] grid {prec}: k_spmv {ms * 1e3:.1f} us/launch, {by:.0f} B algorithmic", flush=True)
+        return
+    sc = scenes.stacked_boxes(n_cubes=8, cells=16, seed=0)
+    for prec in ("fp64", "mixed"):
+        g = Scene(sc, precision=prec, device=0, stream=stream, **TOL)
+        st = g.step(allow=(0, -7))  # one step: the matrix below carries its contact blocks
+        xb, _ = g.get_state()
+        x = np.concatenate([xb, sc["obs_pos"]])
+        _, _, n_active = g.linearize(x, sigma=st["sigma"])
+        rhs = np.random.default_rng(0).normal(size=(g.n_all, 3))
+        _, it, _ = g.solve(rhs, mode=0, rtol=1e-30, max_iters=64)
+        ms, by = g.spmv_benchmark(reps=8)
+        g.close()
+        print(f"[traffic] boxes {prec}: {n_active} active pairs; PCG {it} iterations; k_spmv {ms * 1e3:.2f} us, "
+              f"{by:.0f} B algorithmic per SpMV", flush=True)
+
+
+def mode_large(stream, ccd_rule):
+    import scenes
+    from paper_2407_00046_amd import Scene
+    out = {}
+    for E_net in (1e9, 1e8):
+        sc = scenes.chain_net_large(E_net=E_net)
+        print(f"[bench] {sc['name']} E_net {E_net:g}: {sc['tets'].shape[0]} tets, {sc['rest_pos'].shape[0]} vertices",
+              flush=True)
+        for prec in ("fp64", "mixed"):
+            g = Scene(sc, precision=prec, device=0, stream=stream, ccd_rule=ccd_rule, **TOL)
+            st = g.step(allow=(0, -7))
+            g.close()
+            rec = {k: st[k] for k in ("status", "converged", "newton_iters", "pcg_iters", "warm_iters", "n_active_max",
+                                      "n_aug_max", "ls_retries", "sec_total", "sec_pcg", "min_dist")}
+            out[f"E{E_net:g}_{prec}"] = rec
+            print(f"[bench] large net E {E_net:g} {prec}: {rec}", flush=True)
+    print(json.dumps(dict(metric=METRIC, workload="chain_net_large_1.76M_tets_1_frame", ccd_rule=ccd_rule,
+                          results=out)), flush=True)
+
+
+def mode_ablations(sc, steps, stream, ccd_rule):
+    out = {}
+    for name, kw in (("bal", {}), ("no_warm_start", dict(warm_start=0)), ("no_al", dict(use_al=0))):
+        r, _ = run_fp64(sc, steps, 0, stream, ccd_rule=ccd_rule, **kw)
+        r.pop("per_step")
+        out[name] = r
+        print(f"[bench] ablation {name}: {r['s_per_step']:.3f} s/step, {r['newton_iters_per_step']:.1f} Newton, "
+              f"{r['pcg_iters_per_step']:.0f} PCG + {r['warm_iters_per_step']:.0f} warm per step", flush=True)
+    print(json.dumps(dict(metric=METRIC, workload=sc["name"], ablations=out)), flush=True)
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10, help="timed steps (the workload has 10)")
+    ap.add_argument("--steps", type=int, default=10, help="timed steps (the workload has 10; more walk it again)")
     ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--cells", type=int, default=16)
+    ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-r1", action="store_true", help="skip the 128^3-grid SpMV roofline")
+    ap.add_argument("--ccd-rule", default="printed", choices=["printed", "half_gap", "literal"])
+    ap.add_argument("--large", action="store_true")
+    ap.add_argument("--ablations", action="store_true")
+    ap.add_argument("--traffic", choices=["boxes", "grid"])
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding of this path is a "
@@ -187,44 +350,44 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.init()
     stream = torch.cuda.current_stream().cuda_stream
-    sc = scenes.stacked_boxes(n_cubes=8, cells=args.cells, seed=0)
+    if args.traffic:
+        mode_traffic(args.traffic, stream)
+        return
+    if args.large:
+        mode_large(stream, args.ccd_rule)
+        return
+    sc = scenes.stacked_boxes(n_cubes=8, cells=16, seed=0)
     print(f"[bench] workload {sc['name']}: {sc['tets'].shape[0]} tets, {sc['rest_pos'].shape[0]} vertices", flush=True)
-    mixed, xm = run_precision(sc, "mixed", args.steps, args.warmup, stream)
-    print(f"[bench] mixed: {mixed['s_per_step']:.3f} s/step", flush=True)
-    fp64 = None
-    if not args.no_fp64:
-        fp64, xf = run_precision(sc, "fp64", args.steps, args.warmup, stream, replay=False)
-        print(f"[bench] fp64: {fp64['s_per_step']:.3f} s/step", flush=True)
-        L = np.linalg.norm(sc["x0"].max(0) - sc["x0"].min(0))
-        mixed["eps_x_vs_fp64"] = float(np.linalg.norm(xm - xf, axis=1).max() / L)
+    if args.ablations:
+        mode_ablations(sc, args.steps, stream, args.ccd_rule)
+        return
+    fp64, states = run_fp64(sc, args.steps, args.warmup, stream, ccd_rule=args.ccd_rule)
+    print(f"[bench] fp64: {fp64['s_per_step']:.3f} s/step", flush=True)
+    mixed = None
+    if not args.no_mixed:
+        mixed = run_mixed_from(sc, states, args.steps, stream, ccd_rule=args.ccd_rule)
+        print(f"[bench] mixed: {mixed['s_per_step']:.3f} s/step, max one-step eps_x vs fp64 "
+              f"{mixed['eps_x_vs_fp64_max']:.2e}", flush=True)
     r1 = None
     if not args.no_r1:
         r1 = spmv_r1(stream)
-        r1["copy_peak_gbs"] = copy_peak_gbs(stream)
-        print(f"[bench] streaming copy: {r1['copy_peak_gbs']:.0f} GB/s", flush=True)
+        r1["stream_peak"] = stream_peak()
+        print(f"[bench] streaming read {r1['stream_peak']['read_gbs']:.0f} GB/s, copy "
+              f"{r1['stream_peak']['copy_gbs']:.0f} GB/s", flush=True)
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(sc, mixed["newton_iters_per_step"])
+        cpu = cpu_baseline(fp64["newton_iters_per_step"])
         print(f"[bench] cpu oracle sample: {cpu['sample']}", flush=True)
-    ach = mixed.get("spmv_gbs")
-    roof = None
-    if ach:
-        kern = "k_cg_dir_spmv<float,float>"
-        rec = recorded_traffic(kern)
-        roof = dict(bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
-                    traffic=rec["bytes_per_launch"] if rec else None, kernel=kern,
-                    bytes_per_launch=mixed["spmv_bytes"], avg_launch_ms=mixed["spmv_ms_avg"])
-        if rec:
-            roof["traffic_note"] = (f"PMC on the same kernel source: {rec['bytes_per_launch']} B per launch vs "
-                                    f"{rec['algorithmic_bytes_probe']} B algorithmic on the probe's matrix")
     line = dict(
-        metric="s/timestep & PCG iters/s, mixed vs FP64 at 1e-4 tol; BSR SpMV HBM GB/s",
-        value=mixed["s_per_step"], unit="s/step", n_gpus=1, steps=args.steps, warmup=args.warmup,
-        ms_per_step=1e3 * mixed["s_per_step"], higher_is_better=False, scaling="weak", vs_baseline=None,
-        dtype="mixed f32/f64", data="synthetic",
+        metric=METRIC, value=fp64["s_per_step"], unit="s/step", n_gpus=1, steps=args.steps, warmup=args.warmup,
+        ms_per_step=1e3 * fp64["s_per_step"], higher_is_better=False, scaling="weak", vs_baseline=None,
+        dtype="f64", data="synthetic",
         config=dict(workload=sc["name"], n_tets=int(sc["tets"].shape[0]), n_verts=int(sc["rest_pos"].shape[0]),
-                    precision="mixed", dt=sc["dt"], dhat=sc["dhat"], newton_rtol=1e-4, pcg_rtol=1e-4),
-        roofline=roof, cpu_baseline=cpu, spmv_hbm=r1, mixed=mixed, fp64=fp64,
+                    workload_steps=int(sc["n_steps"]), precision="fp64", dt=sc["dt"], dhat=sc["dhat"],
+                    ccd_rule=args.ccd_rule, **TOL),
+        roofline=roofline_of(fp64, "k_cg_dir_spmv<double, double>"), cpu_baseline=cpu, spmv_hbm=r1, fp64=fp64,
+        mixed=mixed,
+        mixed_speedup=(fp64["s_per_step"] / mixed["s_per_step"]) if mixed else None,
     )
     print(json.dumps(line), flush=True)
 

@@ -48,7 +48,9 @@ enum bal_status {
   BAL_E_INVERTED = -5,        /* a tetrahedron with non-positive volume */
   BAL_E_CAPACITY = -6,        /* active pairs exceed max_contacts at every step length */
   BAL_E_NO_CONVERGENCE = -7,  /* max_newton reached; the last iterate is kept */
-  BAL_E_STATE = -8            /* call out of order (e.g. solve before linearize) */
+  BAL_E_STATE = -8,           /* call out of order (e.g. solve before linearize) */
+  BAL_E_INDEFINITE = -9       /* bal_step_adjoint: the unprojected Hessian at x_{t+1} is not
+                                 positive definite (PCG met p.q <= 0); no gradient is returned */
 };
 
 enum bal_precision {
@@ -172,7 +174,11 @@ int bal_set_youngs(bal_scene *s, const double *youngs, int on_device);
  *   gx_t = (M/h^2) lam - gv_next / h,   gv_t = (M/h) lam,
  *   gE_accum[e] += -lam_e . grad Psi_e(x_{t+1}) / E_e.
  * All arrays body-vertex sized [n_verts][3] except gE_accum [n_tets].
- * The scene's state is left at (x_{t+1}, v_{t+1}). */
+ * The scene's state is left at (x_{t+1}, v_{t+1}).
+ * Errors: BAL_E_NO_CONVERGENCE if the re-solved step does not converge or the
+ * adjoint PCG stays above 1e-10 relative residual, BAL_E_INDEFINITE if H is
+ * not positive definite; in either case no output (gE_accum included) is
+ * written. */
 int bal_step_adjoint(bal_scene *s, const double *x_t, const double *v_t,
                      const double *gx_next, const double *gv_next,
                      double *gx_t, double *gv_t, double *gE_accum,
@@ -255,6 +261,13 @@ int bal_candidates(bal_scene *s, const double *x_all, const double *p_all, int32
  * once (9 scalars + a 4-byte index), the N diagonal blocks, a 4-byte row
  * offset per row, one read of the input and one write of the output. */
 int bal_spmv_benchmark(bal_scene *s, int32_t n_reps, double *ms_per_launch, double *bytes);
+
+/* Streaming-bandwidth reference for the rooflines above: on device `device`,
+ * times n_reps launches of a read of n_bytes (summed, so every load is used)
+ * and of a copy of n_bytes into a second buffer; reports bytes moved per
+ * second in GB/s (the copy counts its reads and writes).  Allocates and frees
+ * its own two buffers of n_bytes (n_bytes >= 1 MiB). */
+int bal_stream_benchmark(int32_t device, int64_t n_bytes, int32_t n_reps, double *read_gbs, double *copy_gbs);
 
 #ifdef __cplusplus
 }

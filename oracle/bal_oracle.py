@@ -64,6 +64,7 @@ CASE_KIND = {0: PTK, 1: PE, 2: PE, 3: PE, 4: PP, 5: PP, 6: PP, 7: EEK, 8: PE, 9:
              10: PE, 11: PE, 12: PP, 13: PP, 14: PP, 15: PP}
 PARALLEL_EPS = 1e-12   # ||e1 x e2||^2 < eps ||e1||^2 ||e2||^2 => parallel edges (sin < 1e-6)
 CCD_EPS = 1e-12        # root interval [-eps, 1+eps] and activation d_TOC < eps + dhat
+COPLANAR_ULPS = 32.0   # start frame coplanar: |det| <= 32 u max|x| (|u||v| + |v||w| + |w||u|)
 
 
 def _dz_sign(v):
@@ -795,7 +796,13 @@ class OracleScene:
         A root at |t| <= eps coincides with the start frame t0 = 0 of the
         candidate times and is not a time of impact (reading: activating it
         bounds every later step of a pair that an iterate left coplanar
-        inside dhat at alpha_max = 0).
+        inside dhat at alpha_max = 0).  So does the root of a pair whose start
+        configuration is coplanar to within the rounding of its positions
+        (|det| <= 32 u max|x_k| (|u||v| + |v||w| + |w||u|), u the unit
+        roundoff): the cubic's constant term is then taken as 0, so its root
+        at t0 is exact however short the step is (reading: a step cut at a
+        coplanar time leaves the pair there, and for a short direction the
+        rounding of the landing point alone moves that root past eps).
 
         Other rules: "literal" activates roots at |t| <= eps as well;
         "half_gap" (a departure from the printed rule) takes half the pair's
@@ -816,6 +823,11 @@ class OracleScene:
         w0 = np.where(pt, X0[:, 3] - X0[:, 1], X0[:, 3] - X0[:, 0])
         w1 = np.where(pt, P[:, 3] - P[:, 1], P[:, 3] - P[:, 0])
         c3, c2, c1, c0 = self._cubic_coeffs(u0, u1, v0, v1, w0, w1)
+        rule = self.p.ccd_rule
+        if rule != "literal":
+            nu, nv, nw = (np.linalg.norm(a, axis=1) for a in (u0, v0, w0))
+            xmax = np.abs(X0).max(axis=(1, 2))
+            c0 = np.where(np.abs(c0) <= COPLANAR_ULPS * 2.0 ** -53 * xmax * (nu * nv + nv * nw + nw * nu), 0.0, c0)
         roots = self.cubic_roots(c3, c2, c1, c0)
         ee = pairs.kind == 1
         if ee.any():
@@ -828,7 +840,6 @@ class OracleScene:
             skip = np.zeros(K, bool)
             skip[ee] = par(X0[ee]) & par(X1[ee])
             roots[skip] = np.nan
-        rule = self.p.ccd_rule
         if rule not in ("printed", "half_gap", "literal"):
             raise ValueError(rule)
         margin = np.full(K, self.dhat)

@@ -23,6 +23,7 @@ _lib = C.CDLL(LIB_PATH)
 
 BAL_OK, BAL_E_INVALID_ARG, BAL_E_OOM, BAL_E_HIP = 0, -1, -2, -3
 BAL_E_PENETRATION, BAL_E_INVERTED, BAL_E_CAPACITY, BAL_E_NO_CONVERGENCE, BAL_E_STATE = -4, -5, -6, -7, -8
+BAL_E_INDEFINITE = -9
 BAL_FP64, BAL_MIXED = 0, 1
 BAL_CCD_PRINTED, BAL_CCD_HALF_GAP, BAL_CCD_LITERAL = 0, 1, 2
 CCD_RULES = {"printed": BAL_CCD_PRINTED, "half_gap": BAL_CCD_HALF_GAP, "literal": BAL_CCD_LITERAL}
@@ -95,6 +96,7 @@ bal_solve = _sig("bal_solve", C.c_int, _vp, _vp, _vp, C.c_int, C.c_double, C.c_i
 bal_ccd_bound = _sig("bal_ccd_bound", C.c_int, _vp, _vp, _vp, _dp)
 bal_candidates = _sig("bal_candidates", C.c_int, _vp, _vp, _vp, C.c_int32, _vp, _vp, _vp, _ip)
 bal_spmv_benchmark = _sig("bal_spmv_benchmark", C.c_int, _vp, C.c_int32, _dp, _dp)
+bal_stream_benchmark = _sig("bal_stream_benchmark", C.c_int, C.c_int32, C.c_int64, C.c_int32, _dp, _dp)
 
 EXPORTED = [n for n in dir() if n.startswith("bal_") and callable(globals()[n])
             and n not in ("bal_scene_desc", "bal_step_stats", "bal_al_state")]
@@ -114,6 +116,14 @@ def _check(code, where, ok=(BAL_OK,)):
 
 def _ptr(a):
     return a.ctypes.data_as(C.c_void_p) if a is not None else None
+
+
+def stream_benchmark(device=0, n_bytes=2 << 30, reps=20):
+    """(read GB/s, copy GB/s) of the library's streaming kernels (bal_stream_benchmark)."""
+    r, c = C.c_double(), C.c_double()
+    _check(bal_stream_benchmark(int(device), int(n_bytes), int(reps), C.byref(r), C.byref(c)),
+           "bal_stream_benchmark")
+    return r.value, c.value
 
 
 class Scene:
@@ -307,7 +317,7 @@ class Scene:
         gv = np.zeros((self.n_verts, 3))
         st = bal_step_stats()
         _check(bal_step_adjoint(self.h, *[_ptr(a) for a in arrs], _ptr(gx), _ptr(gv), _ptr(gE_accum), 0,
-                                C.byref(st)), "bal_step_adjoint", ok=(BAL_OK, BAL_E_NO_CONVERGENCE))
+                                C.byref(st)), "bal_step_adjoint")
         return gx, gv
 
 
@@ -320,7 +330,9 @@ def _make_rollout():
         forward(E [n_tets], v0 [n_verts, 3], scene, x0 [n_verts, 3], n_steps, every)
         keeps (x_t, v_t) every `every` steps; backward re-runs each segment
         from its checkpoint and walks it in reverse through bal_step_adjoint.
-        Gradients flow to E and v0 (float64 tensors).
+        Gradients flow to E and v0 (float64 tensors).  A step that does not
+        converge, in either pass, raises BalError: the gradient is that of the
+        converged step map only.
         """
 
         @staticmethod
@@ -334,7 +346,7 @@ def _make_rollout():
             for t in range(n_steps):
                 if t % every == 0:
                     ckpt[t] = scene.get_state()
-                scene.step(allow=(BAL_OK, BAL_E_NO_CONVERGENCE))
+                scene.step()
             xT, vT = scene.get_state()
             ctx.scene, ctx.ckpt, ctx.n_steps, ctx.every, ctx.Ed = scene, ckpt, n_steps, every, Ed
             return torch.from_numpy(xT).to(v0.device)
@@ -354,7 +366,7 @@ def _make_rollout():
                 scene.set_state(xs, vs)
                 for _ in range(s0, s1):
                     states.append(scene.get_state())
-                    scene.step(allow=(BAL_OK, BAL_E_NO_CONVERGENCE))
+                    scene.step()
                 for t in reversed(range(s1 - s0)):
                     x_t, v_t = states[t]
                     gx, gv = scene.step_adjoint(x_t, v_t, gx, gv, gE)

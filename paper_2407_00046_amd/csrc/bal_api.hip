@@ -381,6 +381,9 @@ static int newton_solve(Scene &s, bal_step_stats *st, bool record) {
   S.sec_collision += since(tc);
   double prev_min = INFINITY, e0 = -1.0;
   int status = BAL_E_NO_CONVERGENCE;
+  // the last line search that accepted no step rejected some trial only for
+  // exceeding the active-pair memory limit (Sec. 5.2)
+  bool cap_blocked = false;
   for (int l = 0; l < d.max_newton; ++l) {
     tc = clk::now();
     launch_pair_distance(s, s.cand, x, s.cand.d.as<double>(), s.cand.cs.as<int>());
@@ -460,15 +463,17 @@ static int newton_solve(Scene &s, bal_step_stats *st, bool record) {
       int valid, nact;
       if ((rc = energy_at(s, x, s.cand2, sig, &L0, &valid, &nact))) return rc;
       alpha = amax;
-      bool accepted = false;
+      bool accepted = false, over_cap = false;
       while (alpha >= 1e-9) {
         launch_axpy_state(s, xtr, x, dx, alpha, 3 * s.N);
         double L;
         if ((rc = energy_at(s, xtr, s.cand2, sig, &L, &valid, &nact))) return rc;
         if (valid && nact <= d.max_contacts && L <= L0) { accepted = true; break; }
+        if (valid && L <= L0) over_cap = true;
         alpha *= 0.5;
       }
       S.sec_linesearch += since(tl);
+      cap_blocked = !accepted && over_cap;
       if (accepted) break;
       if (conv || retries >= 10) {
         alpha = 0.0;
@@ -513,6 +518,7 @@ static int newton_solve(Scene &s, bal_step_stats *st, bool record) {
     copy3(s, x, xtr);
     std::swap(s.cand, s.cand2);
   }
+  if (status != BAL_OK && cap_blocked) status = BAL_E_CAPACITY;
   hipLaunchKernelGGL(k_velocity, dim3(blocks_for(s.N, 256)), dim3(256), 0, s.stream, s.N, x, s.x_t.as<double>(),
                      s.freev.as<uint8_t>(), 1.0 / d.dt, s.v.as<double>());
   launch_pair_distance(s, s.cand, x, s.cand.d.as<double>(), s.cand.cs.as<int>());
@@ -1098,7 +1104,9 @@ const char *bal_status_string(int status) {
     case BAL_E_PENETRATION: return "initial state has a pair at zero distance";
     case BAL_E_INVERTED: return "inverted or degenerate tetrahedron";
     case BAL_E_CAPACITY: return "active pairs exceed max_contacts";
-    case BAL_E_NO_CONVERGENCE: return "Newton iteration cap reached";
+    case BAL_E_NO_CONVERGENCE: return "not converged (Newton iteration cap, a stalled step, or an adjoint solve "
+                                      "above its tolerance)";
+    case BAL_E_INDEFINITE: return "Hessian not positive definite at the converged state (no adjoint)";
     case BAL_E_STATE: return "call out of order";
     default: return "unknown status";
   }
@@ -1399,6 +1407,87 @@ int bal_candidates(bal_scene *h, const double *x_all, const double *p_all, int32
   return rc;
 }
 
+}  // extern "C"
+
+// Streaming references for the bandwidth roofline: every thread moves four
+// 16-byte words per pass with all four loads issued before any use.  The read
+// kernel sums what it loads (one partial per block) so no load is dead.
+__global__ void __launch_bounds__(256) k_stream_read(const double2 *__restrict__ a, long n, double *__restrict__ part) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  const long stride = (long)gridDim.x * blockDim.x;
+  long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i + 3 * stride < n; i += 4 * stride) {
+    double2 v0 = a[i], v1 = a[i + stride], v2 = a[i + 2 * stride], v3 = a[i + 3 * stride];
+    acc += (v0.x + v0.y) + (v1.x + v1.y) + (v2.x + v2.y) + (v3.x + v3.y);
+  }
+  for (; i < n; i += stride) acc += a[i].x + a[i].y;
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(256) k_stream_copy(const double2 *__restrict__ a, double2 *__restrict__ b, long n) {
+  const long stride = (long)gridDim.x * blockDim.x;
+  long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i + 3 * stride < n; i += 4 * stride) {
+    double2 v0 = a[i], v1 = a[i + stride], v2 = a[i + 2 * stride], v3 = a[i + 3 * stride];
+    b[i] = v0;
+    b[i + stride] = v1;
+    b[i + 2 * stride] = v2;
+    b[i + 3 * stride] = v3;
+  }
+  for (; i < n; i += stride) b[i] = a[i];
+}
+
+extern "C" {
+
+int bal_stream_benchmark(int32_t device, int64_t n_bytes, int32_t n_reps, double *read_gbs, double *copy_gbs) {
+  if (n_bytes < (1 << 20) || n_reps <= 0) return BAL_E_INVALID_ARG;
+  if (hipSetDevice(device) != hipSuccess) return BAL_E_HIP;
+  const long n = (long)(n_bytes / 16);
+  const int grid = 256 * 8, bs = 256;
+  void *a = nullptr, *b = nullptr, *part = nullptr;
+  if (hipMalloc(&a, n * 16) != hipSuccess) return BAL_E_OOM;
+  if (hipMalloc(&b, n * 16) != hipSuccess) { hipFree(a); return BAL_E_OOM; }
+  if (hipMalloc(&part, grid * 8) != hipSuccess) { hipFree(a); hipFree(b); return BAL_E_OOM; }
+  hipStream_t st;
+  hipStreamCreate(&st);
+  hipMemsetAsync(a, 0, n * 16, st);
+  hipEvent_t e0, e1;
+  hipEventCreate(&e0);
+  hipEventCreate(&e1);
+  float ms_r = 0.f, ms_c = 0.f;
+  hipLaunchKernelGGL(k_stream_read, dim3(grid), dim3(bs), 0, st, (const double2 *)a, n, (double *)part);
+  hipEventRecord(e0, st);
+  for (int k = 0; k < n_reps; ++k)
+    hipLaunchKernelGGL(k_stream_read, dim3(grid), dim3(bs), 0, st, (const double2 *)a, n, (double *)part);
+  hipEventRecord(e1, st);
+  hipEventSynchronize(e1);
+  hipEventElapsedTime(&ms_r, e0, e1);
+  hipLaunchKernelGGL(k_stream_copy, dim3(grid), dim3(bs), 0, st, (const double2 *)a, (double2 *)b, n);
+  hipEventRecord(e0, st);
+  for (int k = 0; k < n_reps; ++k)
+    hipLaunchKernelGGL(k_stream_copy, dim3(grid), dim3(bs), 0, st, (const double2 *)a, (double2 *)b, n);
+  hipEventRecord(e1, st);
+  int rc = hip_ok(hipEventSynchronize(e1));
+  hipEventElapsedTime(&ms_c, e0, e1);
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  hipStreamDestroy(st);
+  hipFree(a);
+  hipFree(b);
+  hipFree(part);
+  if (rc) return rc;
+  if (read_gbs) *read_gbs = (double)n * 16 * n_reps / (ms_r * 1e-3) / 1e9;
+  if (copy_gbs) *copy_gbs = 2.0 * n * 16 * n_reps / (ms_c * 1e-3) / 1e9;
+  return BAL_OK;
+}
+
 int bal_spmv_benchmark(bal_scene *h, int32_t n_reps, double *ms_per_launch, double *bytes) {
   if (!h || n_reps <= 0) return BAL_E_INVALID_ARG;
   Scene &s = h->s;
@@ -1430,8 +1519,9 @@ int bal_step_adjoint(bal_scene *h, const double *x_t, const double *v_t, const d
   hipSetDevice(s.dev);
   int rc = bal_set_state(h, x_t, v_t, on_device);
   if (rc) return rc;
+  // the frozen-state derivative exists only at a converged step
   rc = newton_solve(s, stats, false);
-  if (rc != BAL_OK && rc != BAL_E_NO_CONVERGENCE) return rc;
+  if (rc != BAL_OK) return rc;
   size_t nb3 = 3 * (size_t)s.nb, n3 = 3 * (size_t)s.N;
   hipMemcpyKind kin = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
   hipMemcpyKind kout = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
@@ -1461,19 +1551,14 @@ int bal_step_adjoint(bal_scene *h, const double *x_t, const double *v_t, const d
   double rel = 0.0;
   double *lam = s.dx.as<double>();
   rc = pcg_solve(s, s.rhs.as<double>(), lam, bn, cap, 0, 0, &it, &rel);
-  if (rc == BAL_E_NO_CONVERGENCE) {
-    // negative curvature: fall back to the projected Hessian
-    if ((rc = linearize_at(s, x, 1, sig))) {
-      s.desc.pcg_rtol = save;
-      s.desc.pcg_stall_window = save_stall;
-      return rc;
-    }
-    rc = pcg_solve(s, s.rhs.as<double>(), lam, bn, cap, 0, 0, &it, &rel);
-  }
   s.desc.pcg_rtol = save;
   s.desc.pcg_stall_window = save_stall;
-  if (rc == BAL_OK && rel > 1e-10) rc = BAL_E_NO_CONVERGENCE;
-  if (rc != BAL_OK && rc != BAL_E_NO_CONVERGENCE) return rc;
+  if (stats) stats->pcg_iters = it;
+  // p.q <= 0: the unprojected Hessian is not positive definite at x_{t+1}, so
+  // x_{t+1} is no strict minimiser and the step map has no derivative there
+  if (rc == BAL_E_NO_CONVERGENCE) return BAL_E_INDEFINITE;
+  if (rc != BAL_OK) return rc;
+  if (rel > 1e-10) return BAL_E_NO_CONVERGENCE;
   // tet_g holds grad Psi_e at x_{t+1} from the linearization
   DBuf gEd, gxo, gvo, Ed;
   if (gEd.grow((size_t)s.T * 8) || gxo.grow(n3 * 8) || gvo.grow(n3 * 8) || Ed.grow((size_t)s.T * 8)) return BAL_E_OOM;
@@ -1484,14 +1569,12 @@ int bal_step_adjoint(bal_scene *h, const double *x_t, const double *v_t, const d
   hipLaunchKernelGGL(k_adjoint_state, dim3(blocks_for(s.N, 256)), dim3(256), 0, s.stream, s.N, lam,
                      s.grad_b.as<double>(), s.mass.as<double>(), s.freev.as<uint8_t>(), s.desc.dt, gxo.as<double>(),
                      gvo.as<double>());
-  const int status = rc;  // BAL_OK, or BAL_E_NO_CONVERGENCE of the adjoint solve
   hipMemcpyAsync(gE_accum, gEd.p, (size_t)s.T * 8, kout, s.stream);
   rc = export3(s, gxo.as<double>(), gx_t, s.nb, on_device != 0);
   if (!rc) rc = export3(s, gvo.as<double>(), gv_t, s.nb, on_device != 0);
   int rs = sync(s);
-  rc = rc ? rc : (rs ? rs : status);
+  rc = rc ? rc : rs;
   gEd.release(); gxo.release(); gvo.release(); Ed.release();
-  if (stats) stats->pcg_iters = it;
   return rc;
 }
 

@@ -259,6 +259,7 @@ void launch_pair_linearize(Scene &s, const double *x, int project, double sigma)
 
 // ------------------------------------------------------------------- CCD
 constexpr double kCcdEps = 1e-12;
+constexpr double kCoplanarUlps = 32.0;
 
 __device__ __forceinline__ double cubic(double c3, double c2, double c1, double c0, double t) {
   return ((c3 * t + c2) * t + c1) * t + c0;
@@ -360,19 +361,13 @@ __device__ __forceinline__ double sgn(double v) { return v > kCcdEps ? 1.0 : (v 
 // reference time (t_prev + tau) / 2 differ in sign (|sd| <= eps counts as
 // sign 0, so tau never rests on the coplanarity itself); point-point and
 // point-edge cases keep tau.  Rules (bal_ccd_rule): printed, margin = dhat
-// and a root at |t| <= eps is the start frame t0 = 0, not a time of impact;
+// and a root at |t| <= eps is the start frame t0 = 0, not a time of impact,
+// as is the root of a start frame coplanar to within the rounding of its
+// positions (|det| <= 32 u max|x| (|u||v| + |v||w| + |w||u|): constant
+// term taken as 0);
 // half-gap (not in the paper), margin = d0 / 2 for a pair that starts closer
 // than dhat; literal, margin = dhat with roots at |t| <= eps activated.
-__global__ void k_ccd(int n, const int *__restrict__ kind, const int4 *__restrict__ nodes, const double *__restrict__ x,
-                      const double *__restrict__ p, double dhat, int rule, double *__restrict__ tau) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  int4 nd = nodes[i];
-  v3 X0[4], P[4];
-  load_pair(x, nd, X0);
-  load_pair(p, nd, P);
-  int kd = kind[i];
-  tau[i] = 1.0;
+__device__ double pair_toi(int kd, const v3 *X0, const v3 *P, double dhat, int rule) {
   v3 u0, u1, v0, v1, w0, w1;
   if (kd == 0) {
     u0 = X0[0] - X0[1]; u1 = P[0] - P[1];
@@ -385,13 +380,22 @@ __global__ void k_ccd(int n, const int *__restrict__ kind, const int4 *__restric
     v3 X1[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) X1[k] = X0[k] + P[k];
-    if (ee_parallel(X0[1] - X0[0], X0[3] - X0[2]) && ee_parallel(X1[1] - X1[0], X1[3] - X1[2])) return;
+    if (ee_parallel(X0[1] - X0[0], X0[3] - X0[2]) && ee_parallel(X1[1] - X1[0], X1[3] - X1[2])) return 1.0;
   }
   // det[u0 + t u1, v0 + t v1, w0 + t w1] expanded by multilinearity
   double c0 = dot(u0, cross(v0, w0));
   double c1 = dot(u1, cross(v0, w0)) + dot(u0, cross(v1, w0)) + dot(u0, cross(v0, w1));
   double c2 = dot(u1, cross(v1, w0)) + dot(u1, cross(v0, w1)) + dot(u0, cross(v1, w1));
   double c3 = dot(u1, cross(v1, w1));
+  if (rule != BAL_CCD_LITERAL) {
+    // a start frame coplanar to within the rounding of the positions has its
+    // root at t0 exactly (however short p is)
+    double xm = 0.0;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) xm = fmax(xm, fmax(fabs(X0[m].x), fmax(fabs(X0[m].y), fabs(X0[m].z))));
+    const double nu = sqrt(dot(u0, u0)), nv = sqrt(dot(v0, v0)), nw = sqrt(dot(w0, w0));
+    if (fabs(c0) <= kCoplanarUlps * 0x1p-53 * xm * (nu * nv + nv * nw + nw * nu)) c0 = 0.0;
+  }
   double roots[3];
   int nr = cubic_roots(c3, c2, c1, c0, -kCcdEps, 1.0 + kCcdEps, roots);
   double margin = dhat;
@@ -424,11 +428,22 @@ __global__ void k_ccd(int n, const int *__restrict__ kind, const int4 *__restric
           t *= 0.9;
         }
       }
-      tau[i] = t;
-      return;
+      return t;
     }
     tprev = tk;
   }
+  return 1.0;
+}
+
+__global__ void k_ccd(int n, const int *__restrict__ kind, const int4 *__restrict__ nodes, const double *__restrict__ x,
+                      const double *__restrict__ p, double dhat, int rule, double *__restrict__ tau) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int4 nd = nodes[i];
+  v3 X0[4], P[4];
+  load_pair(x, nd, X0);
+  load_pair(p, nd, P);
+  tau[i] = pair_toi(kind[i], X0, P, dhat, rule);
 }
 
 void launch_ccd(Scene &s, const PairList &pl, const double *x, const double *p, double *tau) {
@@ -438,3 +453,4 @@ void launch_ccd(Scene &s, const PairList &pl, const double *x, const double *p, 
 }
 
 }  // namespace bal
+

@@ -149,14 +149,16 @@ def tiny_cube():
                  dt=1.0 / 30.0, dhat=1e-3, n_steps=3)
 
 
-def stacked_boxes(n_cubes=8, cells=16, cell=0.01, gap=0.005, seed=0, E=1e6, nu=0.45, n_steps=10):
+def stacked_boxes(n_cubes=8, cells=16, cell=0.01, gap=0.005, seed=0, E=1e6, nu=0.45, n_steps=10, rotate=True):
     """n_cubes randomly rotated cubes of cells^3 cells, stacked on the y axis.
 
     Each cube is rotated by a uniform random rotation (seeded); cube k+1's
     lowest point sits `gap` above cube k's highest point, and the bottom cube
     sits `gap` above a fixed two-triangle ground plane [-2, 2]^2.
     The default (8 cubes of 16^3 cells, 163,840 tets) is the stacked-boxes
-    workload; small variants serve as parity cases.
+    workload; small variants serve as parity cases.  With rotate=False the
+    cubes stay axis-aligned (face to face; with a gap below dhat every
+    interface is in contact from the start).
     """
     rng = np.random.default_rng(seed)
     base, base_tets = tet_grid(cells, cells, cells, cell)
@@ -166,7 +168,7 @@ def stacked_boxes(n_cubes=8, cells=16, cell=0.01, gap=0.005, seed=0, E=1e6, nu=0
     top = 0.0
     for k in range(n_cubes):
         R = random_rotation(rng)
-        p = base @ R.T
+        p = base @ R.T if rotate else base.copy()
         p[:, 1] += top + gap - p[:, 1].min()
         top = p[:, 1].max()
         pos_all.append(p)

@@ -34,6 +34,15 @@ def compare_whole(sc, prec, n_steps, perturb=0.0):
         st = g.step(allow=(0, -7))
         sigma = st["sigma"]
     x_t, v_t = g.get_state()
+    g.close()
+    compare_at(sc, prec, x_t, v_t, sigma, perturb)
+
+
+def compare_at(sc, prec, x_t, v_t, sigma, perturb=0.0):
+    """Energy, gradient and unprojected Hessian product of a fresh scene at the
+    state (x_t, v_t) (perturbed by `perturb`) against the oracle's."""
+    g = gpu_scene(sc, prec)
+    g.set_state(x_t, v_t)
     nb = x_t.shape[0]
     obs = np.asarray(sc["obs_pos"]).reshape(-1, 3)
     rng = np.random.default_rng(11)
@@ -83,8 +92,14 @@ def test_chain_net_full_size_near_rest():
     compare_whole(scenes.chain_net(), "mixed", 0, perturb=1e-5)
 
 
-def compare_sampled(sc, prec, n_sample=48, perturb=0.0):
+def compare_sampled(sc, prec, n_sample=48, perturb=0.0, at_end=False):
+    """Gradient and unprojected Hessian product rows at sampled free vertices,
+    against the oracle on the sub-mesh of their tets.  With at_end the state
+    (x0, v0) is a step's end state, where pairs may be inside dhat: the
+    linearization is taken with sigma = 0, so every row is its elastic and
+    inertial part alone on both sides."""
     g = gpu_scene(sc, prec)
+    g.set_state(sc["x0"], sc["v0"])
     n = sc["rest_pos"].shape[0]
     rng = np.random.default_rng(12)
     xb = sc["x0"] + perturb * rng.uniform(-1.0, 1.0, size=sc["x0"].shape) * (sc["fixed"] == 0)[:, None]
@@ -93,7 +108,8 @@ def compare_sampled(sc, prec, n_sample=48, perturb=0.0):
     e_g, grad_g, na = g.linearize(x, sigma=0.0, project=False)
     hv_g = g.hessian_apply(v)
     g.close()
-    assert na == 0
+    if not at_end:
+        assert na == 0
     free = np.nonzero(sc["fixed"] == 0)[0]
     pick = rng.choice(free, size=n_sample, replace=False)
     sub, used, remap = sub_scene(sc, pick)
@@ -121,34 +137,67 @@ def test_chain_net_large_sampled_rows():
     compare_sampled(scenes.chain_net_large(), "mixed", perturb=1e-5)
 
 
-def test_chain_net_step_properties():
-    """One FP64 step of the chain net (401,280 tets, E = 1e9 links) with a
-    2000-iteration PCG stagnation window (the paper's 100 stops these stiff
-    solves far from their tolerance): the Newton test passes, no tet inverts,
-    every surface pair keeps d > 0 (the oracle's distances at the end state,
-    on its own candidate pairs) and the fixed rings stay put.  In mixed
-    precision the outcome of this step turns on FP32 rounding order (it
-    converged after 250 and 367 Newton iterations with two builds and stalled
-    at 3e-4 with a third), so the property is checked where it holds: FP64
-    converges in about 105 Newton iterations with full steps."""
-    from paper_2407_00046_amd import Scene
-    sc = scenes.chain_net()
-    g = Scene(sc, precision="fp64", newton_rtol=1e-4, pcg_rtol=1e-4, max_newton=400, pcg_stall_window=2000,
-              device=0)
-    st = g.step(allow=(0, -7))
-    x1, v1 = g.get_state()
-    g.close()
-    print(f"chain net step: status {st['status']}, {st['newton_iters']} Newton, {st['pcg_iters']} PCG iterations, "
-          f"{st['n_active_max']} active pairs, {st['sec_total']:.1f} s")
-    assert st["converged"] == 1
+def end_state_checks(sc, x1, v1):
+    """No tet inverted, every surface pair at d > 0 (the oracle's distances on
+    its own candidate pairs), fixed vertices where they started."""
     o = OracleScene(sc, Params(pair_mode="kdtree"))
     x = np.concatenate([x1, np.asarray(sc["obs_pos"]).reshape(-1, 3)])
-    pos, tets = x, sc["tets"].astype(np.int64)
-    e = pos[tets[:, 1:]] - pos[tets[:, :1]]
+    tets = sc["tets"].astype(np.int64)
+    e = x[tets[:, 1:]] - x[tets[:, :1]]
     assert np.einsum("ij,ij->i", e[:, 0], np.cross(e[:, 1], e[:, 2])).min() > 0.0
     pairs = o.candidate_pairs(x)
     d, _ = o.distances(x, pairs)
     assert d.min() > 0.0
-    # fixed rings stay put
     fx = sc["fixed"] == 1
     assert np.array_equal(x1[fx], sc["x0"][fx]) and np.all(v1[fx] == 0.0)
+    return float(d.min())
+
+
+def test_chain_net_as_configured():
+    """The chain net as its workload states it: mixed precision, 5 steps,
+    tolerances 1e-4, App. B's 100-iteration stagnation window and the printed
+    CCD rule of Sec. 5.3.  Each step must end in BAL_OK or
+    BAL_E_NO_CONVERGENCE (recorded, not asserted: with these stiff links,
+    E = 1e9, the method as printed does not reach the gradient test) at a
+    feasible state; the end state's energy, gradient and unprojected Hessian
+    product then match the oracle's at full size."""
+    from paper_2407_00046_amd import Scene
+    sc = scenes.chain_net()
+    g = Scene(sc, precision="mixed", newton_rtol=1e-4, pcg_rtol=1e-4, device=0)
+    sigma = 0.0
+    for k in range(5):
+        st = g.step(allow=(0, -7))
+        x1, v1 = g.get_state()
+        dmin = end_state_checks(sc, x1, v1)
+        sigma = st["sigma"]
+        print(f"chain net step {k}: status {st['status']}, converged {st['converged']}, {st['newton_iters']} Newton, "
+              f"{st['pcg_iters']} PCG iterations, {st['n_active_max']} active pairs, min d {dmin:.3e}, "
+              f"{st['sec_total']:.1f} s")
+        assert st["status"] in (0, -7)
+    g.close()
+    compare_at(sc, "mixed", x1, v1, sigma)
+
+
+@pytest.mark.parametrize("E_net,prec", [(1e9, "fp64"), (1e8, "mixed")])
+def test_chain_net_large_one_frame(E_net, prec):
+    """The large chain net (1,762,560 tets), one frame: status OK or
+    NO_CONVERGENCE (recorded), a feasible end state, and oracle parity of the
+    gradient and unprojected Hessian product on sampled rows there."""
+    from paper_2407_00046_amd import Scene
+    sc = scenes.chain_net_large(E_net=E_net)
+    g = Scene(sc, precision=prec, newton_rtol=1e-4, pcg_rtol=1e-4, device=0)
+    st = g.step(allow=(0, -7))
+    x1, v1 = g.get_state()
+    g.close()
+    print(f"large chain net E {E_net:g} {prec}: status {st['status']}, converged {st['converged']}, "
+          f"{st['newton_iters']} Newton, {st['pcg_iters']} PCG iterations, {st['n_active_max']} active pairs, "
+          f"{st['sec_total']:.1f} s")
+    assert st["status"] in (0, -7)
+    tets = sc["tets"].astype(np.int64)
+    e = x1[tets[:, 1:]] - x1[tets[:, :1]]
+    assert np.einsum("ij,ij->i", e[:, 0], np.cross(e[:, 1], e[:, 2])).min() > 0.0
+    fx = sc["fixed"] == 1
+    assert np.array_equal(x1[fx], sc["x0"][fx])
+    end = dict(sc)
+    end["x0"], end["v0"] = x1, v1
+    compare_sampled(end, prec, at_end=True)

@@ -215,6 +215,23 @@ def test_ccd_root_at_start_frame():
     assert ccd_scene("literal").ccd(x, p, pt_pair()) <= 1e-12
 
 
+def test_ccd_start_frame_coplanar_by_rounding():
+    """A vertex left in the triangle's plane up to rounding (y = 0.1 * 3 - 0.3
+    = 5.6e-17, 5e-4 outside the edge x = 0), leaving along a short direction
+    (1e-9 m down): the cubic's root sits at t = 5.6e-8, far past eps, yet it is
+    the start frame t0, since the start configuration is coplanar to within
+    the rounding of its positions; the printed reading gives no bound there,
+    the literal rule bounds the step at that root."""
+    y0 = 0.1 * 3 - 0.3
+    assert 0.0 < y0 < 1e-16
+    x = np.concatenate([np.array([[-5e-4, y0, 0.5]]), TRI])
+    p = np.zeros((4, 3))
+    p[0, 1] = -1e-9
+    assert ccd_scene("printed").ccd(x, p, pt_pair()) == 1.0
+    a = ccd_scene("literal").ccd(x, p, pt_pair())
+    assert abs(a - y0 / 1e-9) <= 1e-12 * (y0 / 1e-9)
+
+
 def test_ccd_edge_edge_precedes_first_crossing():
     """alpha_max never exceeds the first time two edges pass through each
     other (dense time scan of the line-line signed distance with both
