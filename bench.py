@@ -25,6 +25,8 @@ two of the cubes (face to face, 0.5 mm apart: inside dhat) and scales it by
 Other modes (one JSON line each):
   --large       one frame of the large chain net (1,762,560 tets) in FP64 and mixed
   --ablations   the stacked boxes with warm_start = 0 and with use_al = 0 (FP64)
+  --scale       one step of 60 tumbling blocks (8.9M tets), free and under an
+                active-pair memory limit (the line search's halving, Sec. 5.2)
   --traffic boxes|grid
                 the workload for PMC traffic counters (run under rocprofv3 --pmc):
                 a 512 MiB streaming copy to calibrate the counters, then PCG
@@ -317,6 +319,41 @@ def mode_large(stream, ccd_rule):
                           results=out)), flush=True)
 
 
+def mode_scale(stream, ccd_rule):
+    """One step of the memory-limited scale-up workload (60 tumbling blocks,
+    8.9M tets) in FP64: device memory the scene holds, s/step, Newton and PCG
+    iterations; then the same step with the active-pair memory limit set to a
+    quarter of the pairs the free run activates, so the line search halves
+    (Sec. 5.2)."""
+    import torch
+    import scenes
+    from paper_2407_00046_amd import Scene
+    sc = scenes.tumbling_blocks()
+    print(f"[bench] {sc['name']}: {sc['tets'].shape[0]} tets, {sc['rest_pos'].shape[0]} vertices", flush=True)
+    out = {}
+    limit = None
+    for name in ("free", "limited"):
+        kw = dict(max_contacts=limit) if limit else {}
+        torch.cuda.synchronize()
+        free0, _ = torch.cuda.mem_get_info()
+        g = Scene(sc, precision="fp64", device=0, stream=stream, ccd_rule=ccd_rule, **TOL, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = g.step(allow=(0, -6, -7))
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        free1, _ = torch.cuda.mem_get_info()
+        g.close()
+        rec = {k: st[k] for k in ("status", "converged", "newton_iters", "pcg_iters", "warm_iters", "n_active_max",
+                                  "ls_retries", "sec_pcg", "sec_hessian", "sec_ccd", "sec_collision")}
+        rec.update(s_per_step=wall, device_gib=(free0 - free1) / 2 ** 30, max_contacts=limit)
+        out[name] = rec
+        print(f"[bench] scale {name}: {rec}", flush=True)
+        limit = max(1, rec["n_active_max"] // 4)
+    print(json.dumps(dict(metric=METRIC, workload=sc["name"], n_tets=int(sc["tets"].shape[0]), ccd_rule=ccd_rule,
+                          results=out)), flush=True)
+
+
 def mode_ablations(sc, steps, stream, ccd_rule):
     out = {}
     for name, kw in (("bal", {}), ("no_warm_start", dict(warm_start=0)), ("no_al", dict(use_al=0))):
@@ -339,6 +376,7 @@ def main():
     ap.add_argument("--ccd-rule", default="printed", choices=["printed", "half_gap", "literal"])
     ap.add_argument("--large", action="store_true")
     ap.add_argument("--ablations", action="store_true")
+    ap.add_argument("--scale", action="store_true")
     ap.add_argument("--traffic", choices=["boxes", "grid"])
     args = ap.parse_args()
     if args.gpus != 1:
@@ -355,6 +393,9 @@ def main():
         return
     if args.large:
         mode_large(stream, args.ccd_rule)
+        return
+    if args.scale:
+        mode_scale(stream, args.ccd_rule)
         return
     sc = scenes.stacked_boxes(n_cubes=8, cells=16, seed=0)
     print(f"[bench] workload {sc['name']}: {sc['tets'].shape[0]} tets, {sc['rest_pos'].shape[0]} vertices", flush=True)

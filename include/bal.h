@@ -76,6 +76,13 @@ enum bal_ccd_rule {
                            then bounds every later step at alpha_max = 0) */
 };
 
+/* Broad phase of the candidate pass (Sec. 5.3). */
+enum bal_broad_phase {
+  BAL_BROAD_HASH = 0,  /* spatial hash over dhat-inflated (and swept) boxes (default) */
+  BAL_BROAD_LBVH = 1   /* the paper's linear BVH: 64-bit Morton/index keys, radix sort, radix tree,
+                          bottom-up box fit; the same candidate set as the hash */
+};
+
 typedef struct bal_scene bal_scene;
 
 /* Scene description (read once by bal_create_scene; defaults from bal_desc_defaults). */
@@ -99,6 +106,16 @@ typedef struct bal_scene_desc {
   double sigma_fixed;          /* 0: adaptive barrier stiffness (sigma^0 and growth rule, Sec. 3.4);
                                   > 0: sigma held at this value in every step, so that a step is
                                   the minimiser of one smooth energy (differentiable rollouts) */
+  double friction;             /* friction coefficient chi (Sec. 4.1), default 0 (frictionless):
+                                  D_j = chi lam_j f(|u_j h|) on every pair with a positive normal force,
+                                  its frame (lam_j, normal, barycentric weights) updated per Newton
+                                  iteration (fully-implicit friction) */
+  double eps_v;                /* mollifier threshold eps_v of f (Sec. 4.1); <= 0: dhat (default) */
+  double accept_rtol;          /* 0 (default): a step converges only by the Newton test.  > 0: a step
+                                  whose line search finds no decrease of L at FP64 resolution (no
+                                  measurable move and A' empty) also counts as converged when its
+                                  gradient is within accept_rtol ||e^0|| (the energy's rounding floor
+                                  lies above tight Newton tolerances; see bal_step_stats.stalled) */
   int32_t max_newton;          /* default 1000 */
   int32_t max_pcg;             /* PCG iteration cap per Newton iteration, default 20000 */
   int32_t pcg_stall_window;    /* stop PCG when no new minimum of ||r|| in this many
@@ -109,6 +126,7 @@ typedef struct bal_scene_desc {
   int32_t warm_start;          /* 1: stiffness-grouped block-Jacobi warm start (Sec. 4.2) */
   int32_t use_al;              /* 1: augmentation set A' (BAL); 0: plain barrier */
   int32_t ccd_rule;            /* bal_ccd_rule, default BAL_CCD_PRINTED */
+  int32_t broad_phase;         /* bal_broad_phase, default BAL_BROAD_HASH */
   int32_t sweep_cap;           /* 0 (default): the swept candidate pass halves its sweep only when it
                                   would exceed its work bound (2^28 direct box tests, the memory
                                   limit of Sec. 5.2); n > 0 (departure, not in the paper): also while
@@ -129,13 +147,14 @@ typedef struct bal_step_stats {
   int32_t ls_retries;          /* line searches that fell below alpha 1e-9 and resumed PCG */
   int32_t spmv_launches;       /* PCG product launches timed (when kernel timing is on) */
   int32_t graph_launches;      /* PCG chunks replayed as HIP graphs (0: launched one by one) */
-  int32_t reserved;
+  int32_t stalled;             /* 1 if the step ended with no measurable move (see accept_rtol) */
   double sigma;                /* final penalty sigma (0 if never initialised) */
   double min_dist;             /* min pair distance at the end of the step (dhat if none closer) */
   double sec_total, sec_pcg, sec_hessian, sec_ccd, sec_collision, sec_linesearch;
   double spmv_ms;              /* summed PCG product kernel time (hipEvents; kernel timing on) */
   double spmv_bytes;           /* algorithmic bytes of one PCG product launch at the last matrix:
                                   the symmetric block SpMV plus reading z and writing the new direction */
+  double grad_rel;             /* ||e^l|| / ||e^0|| at the last Newton iterate of the step */
 } bal_step_stats;
 
 /* Fills *d with defaults (all pointers NULL, sizes 0). */
@@ -175,6 +194,7 @@ int bal_set_youngs(bal_scene *s, const double *youngs, int on_device);
  *   gE_accum[e] += -lam_e . grad Psi_e(x_{t+1}) / E_e.
  * All arrays body-vertex sized [n_verts][3] except gE_accum [n_tets].
  * The scene's state is left at (x_{t+1}, v_{t+1}).
+ * Friction (chi > 0) has no adjoint here: BAL_E_INVALID_ARG.
  * Errors: BAL_E_NO_CONVERGENCE if the re-solved step does not converge or the
  * adjoint PCG stays above 1e-10 relative residual, BAL_E_INDEFINITE if H is
  * not positive definite; in either case no output (gE_accum included) is

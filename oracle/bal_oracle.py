@@ -196,6 +196,68 @@ def barrier_torch(d, dh):
     return torch.where(inside, -(safe - dh) ** 2 * torch.log(safe / dh), torch.zeros_like(d))
 
 
+def barrier_d1_np(d, dh):
+    """db/dd = -2 (d - dh) log(d / dh) - (d - dh)^2 / d on 0 < d < dh, 0 for d >= dh."""
+    d = np.asarray(d, dtype=np.float64)
+    dh = np.broadcast_to(np.asarray(dh, dtype=np.float64), d.shape)
+    out = np.zeros_like(d)
+    m = (d > 0) & (d < dh)
+    out[m] = -2.0 * (d[m] - dh[m]) * np.log(d[m] / dh[m]) - (d[m] - dh[m]) ** 2 / d[m]
+    return out
+
+
+def friction_f_torch(q, eps_h):
+    """The friction mollifier f of Sec. 4.1 as a function of q = y^2, y the
+    tangential relative displacement of the step:
+    f(y) = -y^3 / (3 eps_v^2 h^2) + y^2 / (eps_v h) for y < eps_v h, and
+    f(y) = y - eps_v h / 3 beyond (reading: the paper prints the mollified
+    branch only; this is its C1 continuation, whose slope is 1, the kinetic
+    regime).  Written in q so that autograd is exact at q = 0 (the y^3 term
+    and its first two derivatives vanish there)."""
+    small = q < eps_h * eps_h
+    qs = torch.where(q > 0, q, torch.ones_like(q))
+    y3 = torch.where(q > 0, qs ** 1.5, torch.zeros_like(q))
+    inner = -y3 / (3.0 * eps_h * eps_h) + q / eps_h
+    ql = torch.where(small, torch.full_like(q, eps_h * eps_h), q)
+    outer = torch.sqrt(ql) - eps_h / 3.0
+    return torch.where(small, inner, outer)
+
+
+def closest_coeffs(case, X4):
+    """beta (K,4): weights of the 4 stencil nodes such that sum_k beta_k X_k is
+    the vector between the two closest points of each pair's distance case
+    (zero on nodes the case does not use); the parameters come from the
+    case's own closest-point problem (point-edge: segment parameter; point-
+    triangle: barycentrics of the projection; edge-edge: the line-line
+    parameters)."""
+    K = X4.shape[0]
+    beta = np.zeros((K, 4))
+    for i in range(K):
+        c = int(case[i])
+        nd = CASE_NODES[c]
+        k = CASE_KIND[c]
+        X = X4[i]
+        if k == PP:
+            beta[i, nd[0]], beta[i, nd[1]] = 1.0, -1.0
+        elif k == PE:
+            p, a, b = X[nd[0]], X[nd[1]], X[nd[2]]
+            t = float(np.dot(p - a, b - a) / np.dot(b - a, b - a))
+            beta[i, nd[0]], beta[i, nd[1]], beta[i, nd[2]] = 1.0, -(1.0 - t), -t
+        elif k == PTK:
+            p, a, b, cc = X
+            e1, e2 = b - a, cc - a
+            G = np.array([[e1 @ e1, e1 @ e2], [e1 @ e2, e2 @ e2]])
+            u, v = np.linalg.solve(G, [np.dot(p - a, e1), np.dot(p - a, e2)])
+            beta[i] = (1.0, -(1.0 - u - v), -u, -v)
+        else:
+            a0, a1, b0, b1 = X
+            e1, e2, r = a1 - a0, b1 - b0, a0 - b0
+            G = np.array([[e1 @ e1, -(e1 @ e2)], [-(e1 @ e2), e2 @ e2]])
+            sa, sb = np.linalg.solve(G, [-(e1 @ r), e2 @ r])
+            beta[i] = (1.0 - sa, sa, -(1.0 - sb), -sb)
+    return beta
+
+
 def lame(E, nu):
     """Lame parameters from Young's modulus and Poisson ratio."""
     E = np.asarray(E, dtype=np.float64)
@@ -258,16 +320,34 @@ class Pairs:
 
 
 @dataclass
+class Frames:
+    """Friction frames of one Newton iteration (Sec. 4.1): for each pair with
+    a positive normal force at the iterate, that force's magnitude lam, the
+    closest-point weights beta (K,4) and the contact normal n (K,3), held
+    constant while the friction potential is differentiated and during the
+    line search; x_t are the positions at the start of the time step."""
+    pairs: Pairs
+    lam: np.ndarray
+    beta: np.ndarray
+    n: np.ndarray
+    x_t: np.ndarray
+    chi: float
+    eps_h: float
+
+
+@dataclass
 class ALState:
-    """BAL state of one time step (Alg. 1): sigma, sigma0 and the set A' with mu, s."""
+    """BAL state of one time step (Alg. 1): sigma, sigma0 and the set A' with
+    mu, s; plus the friction frames of the current iterate (None: no friction)."""
     sigma: float | None = None
     sigma0: float | None = None
     aug: Pairs = field(default_factory=Pairs.empty)
     mu: np.ndarray = field(default_factory=lambda: np.zeros(0))
     s: np.ndarray = field(default_factory=lambda: np.zeros(0))
+    frames: Frames | None = None
 
     def copy(self):
-        return ALState(self.sigma, self.sigma0, self.aug, self.mu.copy(), self.s.copy())
+        return ALState(self.sigma, self.sigma0, self.aug, self.mu.copy(), self.s.copy(), self.frames)
 
 
 @dataclass
@@ -283,6 +363,10 @@ class Params:
     ccd_rule: str = "printed"     # "printed" (Sec. 5.3), "half_gap" (departure) or "literal"; see ccd
     sweep_cap: float = 0.0        # > 0 (departure): CCD sweep halved while a vertex moves
                                   # more than sweep_cap mean surface edge lengths
+    friction: float = 0.0         # chi (Sec. 4.1); 0: frictionless
+    eps_v: float = 0.0            # mollifier threshold eps_v; <= 0: dhat
+    accept_rtol: float = 0.0      # > 0: a stalled step (no measurable move) with |e| <= accept_rtol |e0|
+                                  # counts as converged (the energy's FP64 rounding floor)
 
 
 # ----------------------------------------------------------------------------
@@ -599,7 +683,59 @@ class OracleScene:
             return None
         elastic = (self._t_vol * nh_density_torch(F, self._t_mu, self._t_lam)).sum()
         contact = self._contact_energy_torch(xt, allp, case, d < self.dhat, sigma, mu, s, aug)
+        if st.frames is not None:
+            contact = contact + self.friction_energy_torch(xt, st.frames)
         return inertia, elastic, contact
+
+    # ------------------------------------------------------------- friction
+    def friction_frames(self, x, x_t, pairs: Pairs, st: ALState):
+        """Frames at iterate x (Sec. 4.1, updated per inexact Newton iteration):
+        every pair of the barrier's support or of A' whose normal force
+        lam = -d(pair energy)/dd is positive, with beta and n from its distance
+        case at x.  None when friction is off or sigma is not yet set."""
+        if not self.p.friction > 0.0 or st.sigma is None:
+            return None
+        allp, mu, s, aug = self._merge_pairs(pairs, st)
+        d, case = self.distances(x, allp)
+        sig = float(st.sigma)
+        f1 = sig * barrier_d1_np(d, self.dhat) + aug * (-mu + sig * barrier_d1_np(d, self.dhat + s))
+        lam = -f1
+        keep = ((d < self.dhat) | aug) & (lam > 0.0)
+        sel = np.nonzero(keep)[0]
+        fp = allp.take(sel)
+        X4 = x[fp.nodes]
+        beta = closest_coeffs(case[sel], X4)
+        n = np.einsum("kj,kjc->kc", beta, X4)
+        eps_v = self.p.eps_v if self.p.eps_v > 0.0 else self.dhat
+        return Frames(fp, lam[sel], beta, n, x_t.copy(), float(self.p.friction), eps_v * self.h)
+
+    @staticmethod
+    def _friction_pair_energy(X12, X12_t, lam, beta, n, chi, eps_h):
+        """chi lam f(|P beta.(X - X_t)|) for one pair, P = I - n n^T / n.n."""
+        dx = (beta[:, None] * (X12 - X12_t).reshape(4, 3)).sum(0)
+        w = dx - (dx * n).sum() / (n * n).sum() * n
+        return chi * lam * friction_f_torch((w * w).sum(), eps_h)
+
+    def friction_energy_torch(self, xt, fr: Frames):
+        if len(fr.pairs) == 0:
+            return xt.sum() * 0.0
+        nd = torch.as_tensor(fr.pairs.nodes)
+        X = xt[nd].reshape(-1, 12)
+        Xt = torch.tensor(fr.x_t[fr.pairs.nodes].reshape(-1, 12), dtype=DT)
+        ef = torch.vmap(lambda a, b, l, be, nn: self._friction_pair_energy(a, b, l, be, nn, fr.chi, fr.eps_h))
+        return ef(X, Xt, torch.tensor(fr.lam, dtype=DT), torch.tensor(fr.beta, dtype=DT),
+                  torch.tensor(fr.n, dtype=DT)).sum()
+
+    def friction_hessians(self, x, fr: Frames, project=True):
+        """Per-pair 12x12 Hessians of the friction potential (PSD by
+        construction; projected like every stencil)."""
+        X = torch.tensor(x[fr.pairs.nodes].reshape(-1, 12), dtype=DT)
+        Xt = torch.tensor(fr.x_t[fr.pairs.nodes].reshape(-1, 12), dtype=DT)
+        hf = torch.vmap(torch.func.hessian(
+            lambda a, b, l, be, nn: self._friction_pair_energy(a, b, l, be, nn, fr.chi, fr.eps_h)))
+        H = hf(X, Xt, torch.tensor(fr.lam, dtype=DT), torch.tensor(fr.beta, dtype=DT),
+               torch.tensor(fr.n, dtype=DT)).numpy()
+        return project_psd(H) if project else 0.5 * (H + np.swapaxes(H, 1, 2))
 
     def hessian_vector_product(self, x, y, pairs: Pairs, st: ALState, v):
         """Exact (unprojected) Hessian of L_sigma at x applied to v, (N, 3):
@@ -677,6 +813,10 @@ class OracleScene:
         if len(allp):
             Hc = self.contact_hessians(x, allp, case, mu, s, aug, sigma, project)
             H = H + self._assemble(Hc, allp.nodes)
+        Hf = None
+        if st.frames is not None and len(st.frames.pairs):
+            Hf = self.friction_hessians(x, st.frames, project)
+            H = H + self._assemble(Hf, st.frames.pairs.nodes)
         md = np.repeat(self.mass[self.free_idx] / self.h ** 2, 3)
         H = (H + scipy.sparse.diags(md)).tocsr()
         if not with_lambda:
@@ -689,6 +829,13 @@ class OracleScene:
             for i in range(len(allp)):
                 nd = [allp.nodes[i][j] for j in CASE_NODES[int(case[i])]]
                 lam_bar = np.trace(Hc[i]) / (3.0 * len(nd))
+                for v in nd:
+                    e[v] += 3.0 * lam_bar
+        if Hf is not None:
+            fr = st.frames
+            for i in range(len(fr.pairs)):
+                nd = [fr.pairs.nodes[i][j] for j in range(4) if fr.beta[i, j] != 0.0]
+                lam_bar = np.trace(Hf[i]) / (3.0 * len(nd))
                 for v in nd:
                     e[v] += 3.0 * lam_bar
         e += 3.0 * self.mass / self.h ** 2
@@ -940,6 +1087,8 @@ class OracleScene:
                 if s0 is not None:
                     st.sigma0 = st.sigma = s0
             self._log(f"iteration {it}: {len(pairs)} candidate pairs, {int(active.sum())} active", t0)
+            # friction frames at this iterate (Sec. 4.1: updated per inexact Newton iteration)
+            st.frames = self.friction_frames(x, x_t, pairs, st)
             L0, g = self.lagrangian(x, y, pairs, st, with_grad=True)
             e = self.gradient_free(g)
             en = float(np.linalg.norm(e))
@@ -981,6 +1130,7 @@ class OracleScene:
             moved = alpha * float(np.linalg.norm(P[self.free_idx]))
             if moved <= 1e-15 * float(np.linalg.norm(x[self.free_idx])) and len(st.aug) == 0:
                 x = xn
+                converged = en <= p.accept_rtol * e0
                 break  # no measurable step and nothing left to update: stalled (reading)
             # dual and penalty updates (Alg. 1, lines 12-17)
             dn, _ = self.distances(xn, swept)

@@ -27,6 +27,8 @@ BAL_E_INDEFINITE = -9
 BAL_FP64, BAL_MIXED = 0, 1
 BAL_CCD_PRINTED, BAL_CCD_HALF_GAP, BAL_CCD_LITERAL = 0, 1, 2
 CCD_RULES = {"printed": BAL_CCD_PRINTED, "half_gap": BAL_CCD_HALF_GAP, "literal": BAL_CCD_LITERAL}
+BAL_BROAD_HASH, BAL_BROAD_LBVH = 0, 1
+BROAD_PHASES = {"hash": BAL_BROAD_HASH, "lbvh": BAL_BROAD_LBVH}
 
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int32)
@@ -41,9 +43,10 @@ class bal_scene_desc(C.Structure):
         ("obs_pos", _dp), ("obs_tris", _ip), ("x0", _dp), ("v0", _dp),
         ("dt", C.c_double), ("gravity", C.c_double * 3), ("dhat", C.c_double),
         ("newton_rtol", C.c_double), ("pcg_rtol", C.c_double), ("sigma_fixed", C.c_double),
+        ("friction", C.c_double), ("eps_v", C.c_double), ("accept_rtol", C.c_double),
         ("max_newton", C.c_int32), ("max_pcg", C.c_int32), ("pcg_stall_window", C.c_int32),
         ("max_contacts", C.c_int32), ("warm_iters", C.c_int32), ("precision", C.c_int32),
-        ("warm_start", C.c_int32), ("use_al", C.c_int32), ("ccd_rule", C.c_int32), ("sweep_cap", C.c_int32),
+        ("warm_start", C.c_int32), ("use_al", C.c_int32), ("ccd_rule", C.c_int32), ("broad_phase", C.c_int32), ("sweep_cap", C.c_int32),
         ("device", C.c_int32), ("stream", C.c_void_p),
     ]
 
@@ -53,10 +56,11 @@ class bal_step_stats(C.Structure):
         ("newton_iters", C.c_int32), ("pcg_iters", C.c_int32), ("warm_iters", C.c_int32),
         ("n_active_max", C.c_int32), ("n_aug_max", C.c_int32), ("converged", C.c_int32),
         ("ls_retries", C.c_int32), ("spmv_launches", C.c_int32), ("graph_launches", C.c_int32),
-        ("reserved", C.c_int32),
+        ("stalled", C.c_int32),
         ("sigma", C.c_double), ("min_dist", C.c_double), ("sec_total", C.c_double), ("sec_pcg", C.c_double),
         ("sec_hessian", C.c_double), ("sec_ccd", C.c_double), ("sec_collision", C.c_double),
         ("sec_linesearch", C.c_double), ("spmv_ms", C.c_double), ("spmv_bytes", C.c_double),
+        ("grad_rel", C.c_double),
     ]
 
     def as_dict(self):
@@ -131,9 +135,9 @@ class Scene:
 
     `sc` is a scene dict (see scenes/); keyword arguments override the
     bal_scene_desc defaults (precision "fp64" or "mixed", warm_start, use_al,
-    ccd_rule "printed", "half_gap" or "literal", sweep_cap, newton_rtol, pcg_rtol,
+    ccd_rule "printed", "half_gap" or "literal", broad_phase "hash" or "lbvh", sweep_cap, newton_rtol, pcg_rtol,
     max_newton, max_pcg, pcg_stall_window, max_contacts, warm_iters,
-    sigma_fixed, device, stream).
+    sigma_fixed, friction, eps_v, accept_rtol, device, stream).
     """
 
     def __init__(self, sc, precision="fp64", **kw):
@@ -174,6 +178,8 @@ class Scene:
                 setattr(d, k, int(bool(v)))
             elif k == "ccd_rule":
                 d.ccd_rule = CCD_RULES[v] if isinstance(v, str) else int(v)
+            elif k == "broad_phase":
+                d.broad_phase = BROAD_PHASES[v] if isinstance(v, str) else int(v)
             else:
                 setattr(d, k, v)
         self.desc = d

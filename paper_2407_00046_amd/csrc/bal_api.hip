@@ -282,6 +282,7 @@ static int build_union(Scene &s, PairList &pl) {
   size_t w = s.mixed ? 4 : 8;
   if (s.pair_e.grow(P * 8) || s.pair_g.grow(P * 12 * 8) || s.pair_tr.grow(P * 8) || s.pair_blk.grow(P * 144 * w))
     return BAL_E_OOM;
+  if (s.desc.friction > 0.0 && (s.fr.grow(P * 8 * 8) || s.fr_e.grow(P * 8))) return BAL_E_OOM;
   return BAL_OK;
 }
 
@@ -290,7 +291,7 @@ static int build_union(Scene &s, PairList &pl) {
 static int linearize_at(Scene &s, const double *x, int project, double sigma) {
   hipMemsetAsync(s.flags.p, 0, sizeof(int), s.stream);
   launch_elements(s, x, EM_HESS, project);
-  launch_pair_linearize(s, x, project, sigma);
+  launch_pair_linearize(s, x, project, sigma, 1);
   int rc = build_contact_lists(s);
   if (rc) return rc;
   launch_node_assembly(s, x, 1, 1, 1, 1, s.grad.as<double>());
@@ -314,6 +315,11 @@ static int energy_at(Scene &s, const double *xp, PairList &pl, double sigma, dou
   double e = reduce_sum(s, s.tet_e.as<double>(), s.T) + reduce_sum(s, s.node_e.as<double>(), s.N);
   e += reduce_sum(s, s.cand_e.as<double>(), pl.n);
   if (s.n_aug) e += reduce_sum(s, s.aug_e.as<double>(), s.n_aug);
+  // friction potential with the frames of the last linearization (Sec. 4.1)
+  if (s.desc.friction > 0.0 && s.uni.n > 0) {
+    launch_friction_energy(s, xp, s.fr_e.as<double>());
+    e += reduce_sum(s, s.fr_e.as<double>(), s.uni.n);
+  }
   int f = read_flags_and_clear(s);
   *valid = f == 0;
   *L = e;
@@ -331,7 +337,7 @@ static int compute_sigma0(Scene &s, const double *x, PairList &pl, double *out, 
   s.n_aug = 0;  // g_b from the barrier of the active set only
   int rc = build_union(s, pl);
   if (rc) { s.n_aug = saved_aug; return rc; }
-  launch_pair_linearize(s, x, 0, 1.0);
+  launch_pair_linearize(s, x, 0, 1.0, 0);
   rc = build_contact_lists(s);
   s.n_aug = saved_aug;
   if (rc) return rc;
@@ -495,6 +501,7 @@ static int newton_solve(Scene &s, bal_step_stats *st, bool record) {
       s.trace.insert(s.trace.end(), row, row + 8);
     }
     S.newton_iters = l + 1;
+    S.grad_rel = e0 > 0.0 ? enorm / e0 : 0.0;
     if (conv) {
       copy3(s, x, xtr);
       status = BAL_OK;
@@ -506,6 +513,11 @@ static int newton_solve(Scene &s, bal_step_stats *st, bool record) {
       double moved = alpha * std::sqrt(dot_free(s, dx, dx));
       if (moved <= 1e-15 * std::sqrt(dot_free(s, x, x))) {
         copy3(s, x, xtr);
+        S.stalled = 1;
+        if (enorm <= d.accept_rtol * e0) {
+          status = BAL_OK;
+          S.converged = 1;
+        }
         break;
       }
     }
@@ -854,6 +866,8 @@ static int validate_desc(const bal_scene_desc *d) {
     return BAL_E_INVALID_ARG;
   if (!(d->dt > 0.0) || !(d->dhat > 0.0) || !std::isfinite(d->dt) || !std::isfinite(d->dhat)) return BAL_E_INVALID_ARG;
   if (!(d->sigma_fixed >= 0.0) || !std::isfinite(d->sigma_fixed)) return BAL_E_INVALID_ARG;
+  if (!(d->friction >= 0.0) || !std::isfinite(d->friction) || !std::isfinite(d->eps_v)) return BAL_E_INVALID_ARG;
+  if (!(d->accept_rtol >= 0.0) || !std::isfinite(d->accept_rtol)) return BAL_E_INVALID_ARG;
   if (!finite_all(d->rest_pos, 3 * (size_t)d->n_verts) || !finite_all(d->gravity, 3)) return BAL_E_INVALID_ARG;
   if (d->n_tets && (!finite_all(d->youngs, d->n_tets) || !finite_all(d->poisson, d->n_tets) ||
                     !finite_all(d->density, d->n_tets)))
@@ -871,6 +885,7 @@ static int validate_desc(const bal_scene_desc *d) {
     if (d->obs_tris[k] < 0 || d->obs_tris[k] >= d->n_obs_verts) return BAL_E_INVALID_ARG;
   if (d->max_newton <= 0 || d->max_pcg <= 0 || d->precision < 0 || d->precision > 1) return BAL_E_INVALID_ARG;
   if (d->ccd_rule < BAL_CCD_PRINTED || d->ccd_rule > BAL_CCD_LITERAL || d->sweep_cap < 0) return BAL_E_INVALID_ARG;
+  if (d->broad_phase != BAL_BROAD_HASH && d->broad_phase != BAL_BROAD_LBVH) return BAL_E_INVALID_ARG;
   return BAL_OK;
 }
 
@@ -1072,12 +1087,13 @@ void bal_destroy_scene(bal_scene *h) {
                   &s.blk_src_ptr, &s.blk_src, &s.up_ptr, &s.up_ent, &s.ent, &s.perm_d, &s.stage, &s.sv, &s.st, &s.se, &s.x, &s.v, &s.x_t, &s.v_t, &s.y,
                   &s.xtrial, &s.dx, &s.tet_e, &s.tet_g, &s.tet_tr, &s.tet_blk, &s.val, &s.Dblk, &s.Dinv, &s.e_nodes,
                   &s.group, &s.grad, &s.grad_b, &s.uni_flag, &s.uni_aug, &s.pair_e, &s.pair_g, &s.pair_tr,
-                  &s.pair_blk, &s.cdiag_ptr, &s.cdiag_src, &s.coff_ptr, &s.coff_col, &s.coff_src, &s.ccount,
+                  &s.pair_blk, &s.cdiag_ptr, &s.cdiag_src, &s.coff_ptr, &s.coff_col, &s.coff_src, &s.cm_ptr, &s.cm_col, &s.cm_blk, &s.ccount,
                   &s.cfill, &s.aug_kind, &s.aug_a, &s.aug_b, &s.aug_nodes, &s.aug_key, &s.aug_mu, &s.aug_s,
-                  &s.aug_d, &s.aug_e, &s.aug_tmp_mu, &s.aug_tmp_s, &s.hb_lo, &s.hb_hi, &s.hq_lo, &s.hq_hi,
+                  &s.aug_d, &s.aug_e, &s.aug_tmp_mu, &s.aug_tmp_s, &s.fr, &s.fr_e, &s.hb_lo, &s.hb_hi, &s.hq_lo, &s.hq_hi,
                   &s.h_cnt, &s.h_off, &s.h_key, &s.h_prim, &s.h_bcnt, &s.h_bstart, &s.h_bfill, &s.h_skey,
                   &s.h_sprim, &s.h_large, &s.h_nlarge, &s.h_qcnt, &s.h_lcnt, &s.h_qoff, &s.h_out, &s.qoff_pt, &s.out_pt,
-                  &s.qoff_ee, &s.out_ee, &s.r, &s.z, &s.pv, &s.pv2, &s.q, &s.pcg_ctl, &s.warm_ctl, &s.partial, &s.counter,
+                  &s.qoff_ee, &s.out_ee, &s.lb_part, &s.lb_key, &s.lb_key2, &s.lb_tmp, &s.lb_prim, &s.lb_child,
+                  &s.lb_parent, &s.lb_lparent, &s.lb_arrive, &s.lb_ibox, &s.r, &s.z, &s.pv, &s.pv2, &s.q, &s.pcg_ctl, &s.warm_ctl, &s.partial, &s.counter,
                   &s.scan_tmp, &s.red_out, &s.flags, &s.node_e, &s.cand_e, &s.mask, &s.mask_off, &s.tau, &s.rhs, &s.psweep};
   for (DBuf *b : bufs) b->release();
   PairList *pls[] = {&s.cand, &s.cand2, &s.uni, &s.augtmp};
@@ -1516,6 +1532,7 @@ int bal_step_adjoint(bal_scene *h, const double *x_t, const double *v_t, const d
                      bal_step_stats *stats) {
   if (!h || !x_t || !v_t || !gx_next || !gv_next || !gx_t || !gv_t || !gE_accum) return BAL_E_INVALID_ARG;
   Scene &s = h->s;
+  if (s.desc.friction > 0.0) return BAL_E_INVALID_ARG;  // friction is not a potential: no frozen-state adjoint
   hipSetDevice(s.dev);
   int rc = bal_set_state(h, x_t, v_t, on_device);
   if (rc) return rc;

@@ -67,8 +67,10 @@ struct Scene {
   PairList cand, cand2, uni, augtmp;
   DBuf uni_flag, uni_aug;  // barrier on (int), aug index (int)
   DBuf pair_e, pair_g, pair_tr, pair_blk;
+  DBuf fr, fr_e;  // friction frame per union pair: lam, beta[4], n[3] (8 doubles); friction energies
   DBuf cdiag_ptr, cdiag_src, coff_ptr, coff_col, coff_src, ccount, cfill;
-  int n_cdiag = 0, n_coff = 0;
+  DBuf cm_ptr, cm_col, cm_blk;  // merged off-diagonal contact blocks per row (one per distinct column)
+  int n_cdiag = 0, n_coff = 0, n_cm = 0;
   // augmentation set A' (sorted by key)
   int n_aug = 0;
   DBuf aug_kind, aug_a, aug_b, aug_nodes, aug_key, aug_mu, aug_s, aug_d, aug_e;
@@ -78,6 +80,8 @@ struct Scene {
   // hash scratch
   DBuf hb_lo, hb_hi, hq_lo, hq_hi, h_cnt, h_off, h_key, h_prim, h_bcnt, h_bstart, h_bfill, h_skey, h_sprim,
       h_large, h_nlarge, h_qcnt, h_lcnt, h_qoff, h_out, qoff_pt, out_pt, qoff_ee, out_ee;
+  // LBVH scratch
+  DBuf lb_part, lb_key, lb_key2, lb_tmp, lb_prim, lb_child, lb_parent, lb_lparent, lb_arrive, lb_ibox;
   // PCG
   DBuf ent;  // FP32 storage: per row its lower then transposed entries (operand, block), one dummy at the end
   DBuf r, z, pv, pv2, q, pcg_ctl, warm_ctl, partial, counter, scan_tmp, red_out, flags;
@@ -111,7 +115,8 @@ void launch_elements(Scene &s, const double *x, int mode, int project);
 void launch_pair_distance(Scene &s, const PairList &pl, const double *x, double *d, int *cs);
 void launch_pair_barrier_energy(Scene &s, const PairList &pl, const double *x, double sigma, double *e, int *flags);
 void launch_aug_energy(Scene &s, const double *x, double sigma, double *e, double *d, int *flags);
-void launch_pair_linearize(Scene &s, const double *x, int project, double sigma);
+void launch_pair_linearize(Scene &s, const double *x, int project, double sigma, int with_friction);
+void launch_friction_energy(Scene &s, const double *x, double *e);
 void launch_aug_update(Scene &s, const double *x);
 void launch_ccd(Scene &s, const PairList &pl, const double *x, const double *p, double *tau);
 // ----- launchers (k_hash.hip)
@@ -139,6 +144,10 @@ double dot_free(Scene &s, const double *a, const double *b);
 
 // helpers
 int hip_ok(hipError_t e);
+// eps_v h of the friction mollifier (eps_v <= 0 in the description: dhat)
+inline double friction_eps_h(const Scene &s) {
+  return (s.desc.eps_v > 0.0 ? s.desc.eps_v : s.desc.dhat) * s.desc.dt;
+}
 template <typename T> int upload(Scene &s, DBuf &b, const T *src, size_t n) {
   if (b.grow(n * sizeof(T))) return BAL_E_OOM;
   if (n && hipMemcpyAsync(b.p, src, n * sizeof(T), hipMemcpyHostToDevice, s.stream) != hipSuccess) return BAL_E_HIP;

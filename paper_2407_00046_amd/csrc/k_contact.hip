@@ -113,10 +113,19 @@ void launch_aug_update(Scene &s, const double *x) {
 // on the 4 stencil slots, the projected Hessian blocks between the case's
 // nodes (stencil-slot 4x4 grid of 3x3 blocks) and the mean projected
 // eigenvalue tr / (3k).
+// Friction of one pair (Sec. 4.1) at the iterate: the 3x3 tangent stiffness S,
+// the force direction times magnitude gf and the closest-point weights beta of
+// the 4 stencil slots; the stencil's blocks get beta_a beta_b S and its
+// gradient slots beta_a gf (S is positive semi-definite by construction).
+struct PairFriction {
+  bool on;
+  double beta[4], gf[3], S[9];
+};
+
 template <int R, int K>
 __device__ __forceinline__ void finish_pair(double *Hu, const double *gu, const double *W, int cs, int project,
                                             double *gout, double *blk_out, double *tr_out, bool fp32,
-                                            float *blk_out_f) {
+                                            float *blk_out_f, const PairFriction &fr) {
   constexpr int n = 3 * R;
   double L[R * R], Q[K * R];
   reduced_basis<R, K>(W, L, Q);
@@ -131,7 +140,14 @@ __device__ __forceinline__ void finish_pair(double *Hu, const double *gu, const 
 #pragma unroll
     for (int i = 0; i < n; ++i) tr += P[pk<n>(i, i)];
   }
-  *tr_out = tr / (3.0 * K);
+  double trf = 0.0;
+  if (fr.on) {
+    double sb2 = 0.0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) sb2 += fr.beta[j] * fr.beta[j];
+    trf = sb2 * (fr.S[0] + fr.S[4] + fr.S[8]);
+  }
+  *tr_out = tr / (3.0 * K) + trf / (3.0 * K);
   // gradient on the case's local nodes
 #pragma unroll
   for (int j = 0; j < K; ++j) {
@@ -141,6 +157,7 @@ __device__ __forceinline__ void finish_pair(double *Hu, const double *gu, const 
       double s = 0.0;
 #pragma unroll
       for (int i = 0; i < R; ++i) s += W[i * K + j] * gu[3 * i + c];
+      if (fr.on) s += fr.beta[slot] * fr.gf[c];
       gout[3 * slot + c] = s;
     }
   }
@@ -151,6 +168,11 @@ __device__ __forceinline__ void finish_pair(double *Hu, const double *gu, const 
       double blk[9];
       expand_block<R>(P, Q, a, b, blk);
       int sa = kCaseNodes[cs][a], sb = kCaseNodes[cs][b];
+      if (fr.on) {
+        const double ww = fr.beta[sa] * fr.beta[sb];
+#pragma unroll
+        for (int e = 0; e < 9; ++e) blk[e] += ww * fr.S[e];
+      }
       size_t off = (size_t)(sa * 4 + sb) * 9;
       if (fp32) {
 #pragma unroll
@@ -162,12 +184,104 @@ __device__ __forceinline__ void finish_pair(double *Hu, const double *gu, const 
     }
 }
 
+// Closest-point weights of the 4 stencil slots for distance case cs: sum_k
+// beta_k X_k joins the case's two closest points (the barycentric
+// coordinates of the contact stencil, Sec. 4.1).  Point-edge: the segment
+// parameter; point-triangle interior: the barycentrics of the projection;
+// edge-edge interior: the line-line parameters (Gram systems solved with the
+// squared cross product as determinant).
+__device__ void closest_beta(int cs, const v3 *X, double *beta) {
+  beta[0] = beta[1] = beta[2] = beta[3] = 0.0;
+  const int k = kCaseK[cs];
+  if (k == 2) {
+    beta[kCaseNodes[cs][0]] = 1.0;
+    beta[kCaseNodes[cs][1]] = -1.0;
+  } else if (k == 3) {
+    const int n0 = kCaseNodes[cs][0], n1 = kCaseNodes[cs][1], n2 = kCaseNodes[cs][2];
+    const v3 e = X[n2] - X[n1];
+    const double t = dot(X[n0] - X[n1], e) / dot(e, e);
+    beta[n0] = 1.0;
+    beta[n1] = -(1.0 - t);
+    beta[n2] = -t;
+  } else if (cs == 0) {
+    const v3 e1 = X[2] - X[1], e2 = X[3] - X[1], r = X[0] - X[1];
+    const v3 c = cross(e1, e2);
+    const double det = dot(c, c), g11 = dot(e1, e1), g12 = dot(e1, e2), g22 = dot(e2, e2);
+    const double r1 = dot(r, e1), r2 = dot(r, e2);
+    const double u = (r1 * g22 - r2 * g12) / det, v = (g11 * r2 - g12 * r1) / det;
+    beta[0] = 1.0;
+    beta[1] = -(1.0 - u - v);
+    beta[2] = -u;
+    beta[3] = -v;
+  } else {
+    const v3 e1 = X[1] - X[0], e2 = X[3] - X[2], r = X[0] - X[2];
+    const v3 c = cross(e1, e2);
+    const double det = dot(c, c), g11 = dot(e1, e1), g12 = dot(e1, e2), g22 = dot(e2, e2);
+    const double r1 = -dot(e1, r), r2 = dot(e2, r);
+    // [g11 -g12; -g12 g22] [sa; sb] = [r1; r2]
+    const double sa = (r1 * g22 + g12 * r2) / det, sb = (g11 * r2 + g12 * r1) / det;
+    beta[0] = 1.0 - sa;
+    beta[1] = sa;
+    beta[2] = -(1.0 - sb);
+    beta[3] = -sb;
+  }
+}
+
+// Tangential relative displacement of the step, w = P sum_k beta_k (X_k - X_k^t)
+// with P = I - n n^T / n.n (Sec. 4.1: u h), and the mollifier f of |w|
+// (f(y) = -y^3/(3 eps_v^2 h^2) + y^2/(eps_v h) below eps_v h, its C1
+// continuation y - eps_v h / 3 above) with f'(y)/y and f''(y).
+__device__ __forceinline__ void friction_w(const v3 *X, const v3 *Xt, const double *beta, v3 n, double eh, v3 *w,
+                                           double *f, double *fp_y, double *fpp) {
+  v3 du{0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) du = du + beta[k] * (X[k] - Xt[k]);
+  *w = du - (dot(du, n) / dot(n, n)) * n;
+  const double q = dot(*w, *w), y = sqrt(q);
+  if (y < eh) {
+    *f = -q * y / (3.0 * eh * eh) + q / eh;
+    *fp_y = -y / (eh * eh) + 2.0 / eh;
+    *fpp = -2.0 * y / (eh * eh) + 2.0 / eh;
+  } else {
+    *f = y - eh / 3.0;
+    *fp_y = 1.0 / y;
+    *fpp = 0.0;
+  }
+}
+
+__global__ void k_friction_energy(int n, const int4 *__restrict__ nodes, const double *__restrict__ fr,
+                                  const double *__restrict__ x, const double *__restrict__ xt, double chi, double eh,
+                                  double *__restrict__ e) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double *F = fr + (size_t)i * 8;
+  const double lam = F[0];
+  if (!(lam > 0.0)) {
+    e[i] = 0.0;
+    return;
+  }
+  v3 X[4], Xt[4];
+  load_pair(x, nodes[i], X);
+  load_pair(xt, nodes[i], Xt);
+  v3 w;
+  double f, fp_y, fpp;
+  friction_w(X, Xt, F + 1, v3{F[5], F[6], F[7]}, eh, &w, &f, &fp_y, &fpp);
+  e[i] = chi * lam * f;
+}
+
+void launch_friction_energy(Scene &s, const double *x, double *e) {
+  if (s.uni.n == 0) return;
+  hipLaunchKernelGGL(k_friction_energy, dim3(blocks_for(s.uni.n, 256)), dim3(256), 0, s.stream, s.uni.n,
+                     s.uni.nodes.as<int4>(), s.fr.as<double>(), x, s.x_t.as<double>(), s.desc.friction,
+                     friction_eps_h(s), e);
+}
+
 __global__ __launch_bounds__(64) void k_pair_linearize(
     int n, const int *__restrict__ kind, const int4 *__restrict__ nodes, const int *__restrict__ bar_on,
     const int *__restrict__ aug_idx, const double *__restrict__ mu, const double *__restrict__ sl,
     const double *__restrict__ x, double sigma, double dhat, int project, int fp32, double *__restrict__ pe,
     double *__restrict__ pg, void *__restrict__ pblk, double *__restrict__ ptr, int *__restrict__ pcase,
-    int *__restrict__ flags) {
+    int *__restrict__ flags, double chi, double eh, const double *__restrict__ xt, double *__restrict__ fr_out) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   v3 X[4];
@@ -196,6 +310,49 @@ __global__ __launch_bounds__(64) void k_pair_linearize(
     f1 += -m + sigma * barrier_d1(d, dhat + s);
     f2 += sigma * barrier_d2(d, dhat + s);
   }
+  // friction frame at this iterate (lam, beta, n held constant while D is
+  // differentiated and during the line search, Sec. 4.1)
+  PairFriction pf;
+  pf.on = false;
+  if (chi > 0.0) {
+    const double lam = -f1;
+    double *F = fr_out + (size_t)i * 8;
+    F[0] = 0.0;
+    if (lam > 0.0) {
+      v3 Xt[4];
+      load_pair(xt, nodes[i], Xt);
+      closest_beta(cs, X, pf.beta);
+      v3 nv{0.0, 0.0, 0.0};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) nv = nv + pf.beta[k] * X[k];
+      v3 w;
+      double f, fp_y, fpp;
+      friction_w(X, Xt, pf.beta, nv, eh, &w, &f, &fp_y, &fpp);
+      const double cl = chi * lam;
+      e += cl * f;
+      pf.gf[0] = cl * fp_y * w.x;
+      pf.gf[1] = cl * fp_y * w.y;
+      pf.gf[2] = cl * fp_y * w.z;
+      // S = chi lam P [f'/y (I - w^ w^T) + f'' w^ w^T] P = chi lam [f'/y (P - w^ w^T) + f'' w^ w^T]
+      const double nn = dot(nv, nv), q = dot(w, w);
+      const double nc[3] = {nv.x, nv.y, nv.z}, wc[3] = {w.x, w.y, w.z};
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+          const double Pab = (a == b ? 1.0 : 0.0) - nc[a] * nc[b] / nn;
+          const double ww = q > 0.0 ? wc[a] * wc[b] / q : 0.0;
+          pf.S[3 * a + b] = cl * (fp_y * (Pab - ww) + fpp * ww);
+        }
+      pf.on = true;
+      F[0] = lam;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) F[1 + k] = pf.beta[k];
+      F[5] = nv.x;
+      F[6] = nv.y;
+      F[7] = nv.z;
+    }
+  }
   pe[i] = e;
   // chain rule through d = sqrt(q): grad f = f1/(2d) grad q,
   // Hess f = (f2/(4 d^2) - f1/(4 d^3)) grad q grad q^T + f1/(2d) Hess q
@@ -218,7 +375,7 @@ __global__ __launch_bounds__(64) void k_pair_linearize(
     for (int a = 0; a < 9; ++a) g[a] *= c2;
     double W[12];
     case_W(cs, W);
-    finish_pair<3, 4>(H, g, W, cs, project, gout, bd, ptr + i, fp32, bf);
+    finish_pair<3, 4>(H, g, W, cs, project, gout, bd, ptr + i, fp32, bf, pf);
   } else if (k == 3) {
     int n0 = kCaseNodes[cs][0], n1 = kCaseNodes[cs][1], n2 = kCaseNodes[cs][2];
     double qq, g[6], H[36];
@@ -231,7 +388,7 @@ __global__ __launch_bounds__(64) void k_pair_linearize(
     for (int a = 0; a < 6; ++a) g[a] *= c2;
     double W[6];
     case_W(cs, W);
-    finish_pair<2, 3>(H, g, W, cs, project, gout, bd, ptr + i, fp32, bf);
+    finish_pair<2, 3>(H, g, W, cs, project, gout, bd, ptr + i, fp32, bf, pf);
   } else {
     int n0 = kCaseNodes[cs][0], n1 = kCaseNodes[cs][1];
     v3 r = X[n0] - X[n1];
@@ -244,17 +401,19 @@ __global__ __launch_bounds__(64) void k_pair_linearize(
     for (int a = 0; a < 3; ++a) g[a] *= c2;
     double W[2];
     case_W(cs, W);
-    finish_pair<1, 2>(H, g, W, cs, project, gout, bd, ptr + i, fp32, bf);
+    finish_pair<1, 2>(H, g, W, cs, project, gout, bd, ptr + i, fp32, bf, pf);
   }
 }
 
-void launch_pair_linearize(Scene &s, const double *x, int project, double sigma) {
+void launch_pair_linearize(Scene &s, const double *x, int project, double sigma, int with_friction) {
   if (s.uni.n == 0) return;
+  const double chi = with_friction ? s.desc.friction : 0.0;
   hipLaunchKernelGGL(k_pair_linearize, dim3(blocks_for(s.uni.n, 64)), dim3(64), 0, s.stream, s.uni.n,
                      s.uni.kind.as<int>(), s.uni.nodes.as<int4>(), s.uni_flag.as<int>(), s.uni_aug.as<int>(),
                      s.aug_mu.as<double>(), s.aug_s.as<double>(), x, sigma, s.desc.dhat, project, s.mixed ? 1 : 0,
                      s.pair_e.as<double>(), s.pair_g.as<double>(), s.pair_blk.p, s.pair_tr.as<double>(),
-                     s.uni.cs.as<int>(), s.flags.as<int>());
+                     s.uni.cs.as<int>(), s.flags.as<int>(), chi, friction_eps_h(s), s.x_t.as<double>(),
+                     chi > 0.0 ? s.fr.as<double>() : nullptr);
 }
 
 // ------------------------------------------------------------------- CCD

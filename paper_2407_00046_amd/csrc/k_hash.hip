@@ -13,6 +13,8 @@
 // queries count first, then write at scanned offsets, and the emit pass sorts
 // each query's segment, so the final list is in canonical (kind, a, b) order
 // with no global sort and no atomics in the output.
+#include <hipcub/hipcub.hpp>
+
 #include "bal_internal.h"
 
 namespace bal {
@@ -364,12 +366,295 @@ static int hash_half(Scene &s, int qtype, int etype, const double *x, const doub
   return P;
 }
 
+// ------------------------------------------------------------------- LBVH
+// The paper's own broad phase (Sec. 5.3), selectable in place of the hash:
+// one linear BVH per half over the entry primitives (triangles for
+// point-triangle, edges for edge-edge), their boxes inflated by dhat (and
+// swept for CCD) exactly as the hash's.  Each entry gets a 64-bit key, the
+// 30-bit Morton code of its box centre (10 bits per axis over the centres'
+// bounding box) in the high word and its index in the low word, so keys are
+// distinct; a radix sort orders them; the binary radix tree over the sorted
+// keys is built one internal node per thread (split at the highest differing
+// key bit), and boxes are fitted bottom up, each internal node completed by
+// the second of its two children to arrive.  Queries then descend the tree
+// with a stack and report the same pairs, through the same filters, as the
+// hash; the emit pass sorts each query's segment, so both broad phases return
+// the same canonical list.
+constexpr int kLbvhStack = 72;  // tree depth <= key length (64) + 1
+
+struct LbvhView {
+  int n;                   // leaves
+  const int *leaf_prim;    // entry index of each leaf (sorted order)
+  const int2 *child;       // internal node children: >= 0 internal, < 0 leaf ~c
+  const Box *ibox;         // internal node boxes
+};
+
+__device__ __forceinline__ uint32_t morton30(uint32_t x, uint32_t y, uint32_t z) {
+  uint32_t m = 0;
+#pragma unroll
+  for (int b = 0; b < 10; ++b)
+    m |= (((x >> b) & 1u) << (3 * b + 2)) | (((y >> b) & 1u) << (3 * b + 1)) | (((z >> b) & 1u) << (3 * b));
+  return m;
+}
+
+// Entry boxes and per-block bounds of their centres (lo, hi of 3 axes).
+__global__ void k_lbvh_boxes(int n, int type, const int *sv, const int *st, const int *se, const double *x,
+                             const double *p, double infl, Box *boxes, double *part) {
+  __shared__ double red[6][kHB];
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  double c[3] = {INFINITY, INFINITY, INFINITY}, d[3] = {-INFINITY, -INFINITY, -INFINITY};
+  if (i < n) {
+    Box b = prim_box(type, i, sv, st, se, x, p, infl);
+    boxes[i] = b;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) c[k] = d[k] = 0.5 * (b.lo[k] + b.hi[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) { red[k][threadIdx.x] = c[k]; red[3 + k][threadIdx.x] = d[k]; }
+  __syncthreads();
+  for (int w = kHB / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        red[k][threadIdx.x] = fmin(red[k][threadIdx.x], red[k][threadIdx.x + w]);
+        red[3 + k][threadIdx.x] = fmax(red[3 + k][threadIdx.x], red[3 + k][threadIdx.x + w]);
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x < 6) part[(size_t)blockIdx.x * 6 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ void k_lbvh_bounds(int nb, const double *part, double *bounds) {
+  __shared__ double red[6][kHB];
+  double c[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+  for (int b = threadIdx.x; b < nb; b += blockDim.x)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      c[k] = fmin(c[k], part[(size_t)b * 6 + k]);
+      c[3 + k] = fmax(c[3 + k], part[(size_t)b * 6 + 3 + k]);
+    }
+#pragma unroll
+  for (int k = 0; k < 6; ++k) red[k][threadIdx.x] = c[k];
+  __syncthreads();
+  for (int w = kHB / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        red[k][threadIdx.x] = fmin(red[k][threadIdx.x], red[k][threadIdx.x + w]);
+        red[3 + k][threadIdx.x] = fmax(red[3 + k][threadIdx.x], red[3 + k][threadIdx.x + w]);
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x < 6) bounds[threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ void k_lbvh_keys(int n, const Box *boxes, const double *bounds, uint64_t *keys) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const Box b = boxes[i];
+  uint32_t q[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double ext = bounds[3 + k] - bounds[k];
+    double t = ext > 0.0 ? (0.5 * (b.lo[k] + b.hi[k]) - bounds[k]) / ext : 0.0;
+    t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+    q[k] = (uint32_t)fmin(t * 1024.0, 1023.0);
+  }
+  keys[i] = ((uint64_t)morton30(q[0], q[1], q[2]) << 32) | (uint64_t)(uint32_t)i;
+}
+
+// common prefix length of sorted keys i and j (-1 outside [0, n))
+__device__ __forceinline__ int lbvh_delta(const uint64_t *k, int n, int i, int j) {
+  if (j < 0 || j >= n) return -1;
+  return __clzll(k[i] ^ k[j]);
+}
+
+// Internal node i of the radix tree over n sorted (distinct) keys: the range
+// of leaves it covers extends from i in the direction of the neighbour with
+// the longer common prefix; it splits where the common prefix of the range
+// ends.  Also the leaves' entry indices and every node's parent.
+__global__ void k_lbvh_tree(int n, const uint64_t *keys, int *leaf_prim, int2 *child, int *parent,
+                            int *leaf_parent) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) leaf_prim[i] = (int)(uint32_t)(keys[i] & 0xffffffffu);
+  if (i >= n - 1) return;
+  const int d = lbvh_delta(keys, n, i, i + 1) - lbvh_delta(keys, n, i, i - 1) >= 0 ? 1 : -1;
+  const int dmin = lbvh_delta(keys, n, i, i - d);
+  int lmax = 2;
+  while (lbvh_delta(keys, n, i, i + lmax * d) > dmin) lmax *= 2;
+  int l = 0;
+  for (int t = lmax / 2; t >= 1; t /= 2)
+    if (lbvh_delta(keys, n, i, i + (l + t) * d) > dmin) l += t;
+  const int j = i + l * d;
+  const int dnode = lbvh_delta(keys, n, i, j);
+  int sp = 0, t = l;
+  do {
+    t = (t + 1) >> 1;
+    if (lbvh_delta(keys, n, i, i + (sp + t) * d) > dnode) sp += t;
+  } while (t > 1);
+  const int gamma = i + sp * d + (d < 0 ? d : 0);
+  const int lo = i < j ? i : j, hi = i < j ? j : i;
+  const int left = lo == gamma ? ~gamma : gamma;
+  const int right = hi == gamma + 1 ? ~(gamma + 1) : gamma + 1;
+  child[i] = make_int2(left, right);
+  if (left < 0) leaf_parent[~left] = i; else parent[left] = i;
+  if (right < 0) leaf_parent[~right] = i; else parent[right] = i;
+  if (i == 0) parent[0] = -1;
+}
+
+__device__ __forceinline__ double ld_acq(const double *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_rel(double *p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Bottom-up fit: one thread per leaf walks to the root; at each internal node
+// the first arrival stops and the second (whose sibling subtree is complete)
+// writes the node's box.  Node boxes go through device-scope atomic loads and
+// stores with a fence before each arrival count, so the second arrival reads
+// the boxes the first one wrote.  Every thread stops after at most depth steps.
+__global__ void k_lbvh_refit(int n, const Box *ebox, const int *leaf_prim, const int2 *child, const int *parent,
+                             const int *leaf_parent, int *arrive, Box *ibox) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int node = leaf_parent[i];
+  for (int step = 0; step < kLbvhStack && node >= 0; ++step) {
+    __threadfence();
+    if (atomicAdd(&arrive[node], 1) == 0) return;
+    __threadfence();
+    const int2 c = child[node];
+    double lo[3], hi[3];
+    const int cc[2] = {c.x, c.y};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) { lo[k] = INFINITY; hi[k] = -INFINITY; }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const double *src = cc[h] < 0 ? (const double *)&ebox[leaf_prim[~cc[h]]] : (const double *)&ibox[cc[h]];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        lo[k] = fmin(lo[k], ld_acq(src + k));
+        hi[k] = fmax(hi[k], ld_acq(src + 3 + k));
+      }
+    }
+    double *dst = (double *)&ibox[node];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) { st_rel(dst + k, lo[k]); st_rel(dst + 3 + k, hi[k]); }
+    node = parent[node];
+  }
+}
+
+// Partners of query q in the tree (edge-edge: only partners t > q); emit(t).
+// Returns false if the descent stack overflowed (cannot happen for a tree of
+// depth <= 64, which the 64-bit keys guarantee).
+template <typename F>
+__device__ bool lbvh_visit(const QueryArgs &A, const LbvhView &T, int q, F emit) {
+  const Box qb = prim_box(A.qtype, q, A.sv, A.st, A.se, A.x, A.p, 0.0);
+  const bool ee = A.qtype == 2;
+  auto leaf = [&](int lf) {
+    const int t = T.leaf_prim[lf];
+    if ((!ee || t > q) && boxes_overlap(qb, A.ebox[t]) && pair_ok(A, q, t)) emit(t);
+  };
+  if (T.n == 0) return true;
+  if (T.n == 1) { leaf(0); return true; }
+  int stack[kLbvhStack];
+  int sp = 0;
+  stack[sp++] = 0;
+  while (sp > 0) {
+    const int2 c = T.child[stack[--sp]];
+    const int cc[2] = {c.x, c.y};
+    for (int h = 0; h < 2; ++h) {
+      if (cc[h] < 0) {
+        leaf(~cc[h]);
+      } else if (boxes_overlap(qb, T.ibox[cc[h]])) {
+        if (sp >= kLbvhStack) return false;
+        stack[sp++] = cc[h];
+      }
+    }
+  }
+  return true;
+}
+
+__global__ void k_lbvh_count(QueryArgs A, LbvhView T, int *qcnt, int *flags) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= A.nq) return;
+  int c = 0;
+  if (!lbvh_visit(A, T, q, [&](int) { ++c; })) atomicOr(flags, 4);
+  qcnt[q] = c;
+}
+
+__global__ void k_lbvh_write(QueryArgs A, LbvhView T, const int *qoff, int *outb) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= A.nq) return;
+  int o = qoff[q];
+  lbvh_visit(A, T, q, [&](int t) { outb[o++] = t; });
+}
+
+static int lbvh_half(Scene &s, int qtype, int etype, const double *x, const double *p, int *qoff_out_n,
+                     DBuf &qoff_buf, DBuf &out_buf) {
+  const int nq = qtype == 0 ? s.nsv : s.nse;
+  const int ne = etype == 1 ? s.nst : s.nse;
+  const int nbk = blocks_for(ne > 0 ? ne : 1, kHB);
+  const size_t E1 = (size_t)(ne > 0 ? ne : 1);
+  if (s.hb_lo.grow((E1 + 1) * sizeof(Box)) || s.lb_part.grow((size_t)nbk * 6 * 8 + 6 * 8) ||
+      s.lb_key.grow(E1 * 8) || s.lb_key2.grow(E1 * 8) || s.lb_prim.grow(E1 * 4) ||
+      s.lb_child.grow(E1 * sizeof(int2)) || s.lb_parent.grow(E1 * 4) || s.lb_lparent.grow(E1 * 4) ||
+      s.lb_arrive.grow(E1 * 4) || s.lb_ibox.grow(E1 * sizeof(Box)))
+    return BAL_E_OOM;
+  Box *ebox = s.hb_lo.as<Box>();
+  double *bounds = s.lb_part.as<double>() + (size_t)nbk * 6;
+  if (ne > 0) {
+    hipLaunchKernelGGL(k_lbvh_boxes, dim3(nbk), dim3(kHB), 0, s.stream, ne, etype, s.sv.as<int>(), s.st.as<int>(),
+                       s.se.as<int>(), x, p, s.desc.dhat, ebox, s.lb_part.as<double>());
+    hipLaunchKernelGGL(k_lbvh_bounds, dim3(1), dim3(kHB), 0, s.stream, nbk, s.lb_part.as<double>(), bounds);
+    hipLaunchKernelGGL(k_lbvh_keys, dim3(nbk), dim3(kHB), 0, s.stream, ne, ebox, bounds, s.lb_key.as<uint64_t>());
+    size_t tmp = 0;
+    if (hipcub::DeviceRadixSort::SortKeys(nullptr, tmp, s.lb_key.as<uint64_t>(), s.lb_key2.as<uint64_t>(), ne, 0, 64,
+                                          s.stream) != hipSuccess)
+      return BAL_E_HIP;
+    if (s.lb_tmp.grow(tmp + 16)) return BAL_E_OOM;
+    if (hipcub::DeviceRadixSort::SortKeys(s.lb_tmp.p, tmp, s.lb_key.as<uint64_t>(), s.lb_key2.as<uint64_t>(), ne, 0,
+                                          64, s.stream) != hipSuccess)
+      return BAL_E_HIP;
+    hipMemsetAsync(s.lb_arrive.p, 0, E1 * 4, s.stream);
+    hipLaunchKernelGGL(k_lbvh_tree, dim3(nbk), dim3(kHB), 0, s.stream, ne, s.lb_key2.as<uint64_t>(),
+                       s.lb_prim.as<int>(), s.lb_child.as<int2>(), s.lb_parent.as<int>(), s.lb_lparent.as<int>());
+    if (ne > 1)
+      hipLaunchKernelGGL(k_lbvh_refit, dim3(nbk), dim3(kHB), 0, s.stream, ne, ebox, s.lb_prim.as<int>(),
+                         s.lb_child.as<int2>(), s.lb_parent.as<int>(), s.lb_lparent.as<int>(), s.lb_arrive.as<int>(),
+                         s.lb_ibox.as<Box>());
+  }
+  QueryArgs A{};
+  A.qtype = qtype; A.etype = etype; A.nq = nq; A.ne = ne;
+  A.sv = s.sv.as<int>(); A.st = s.st.as<int>(); A.se = s.se.as<int>();
+  A.fr = s.freev.as<uint8_t>(); A.nbody = s.nb; A.x = x; A.p = p; A.ebox = ebox;
+  LbvhView T{ne, s.lb_prim.as<int>(), s.lb_child.as<int2>(), s.lb_ibox.as<Box>()};
+  if (s.h_qcnt.grow((size_t)(nq + 1) * sizeof(int)) || qoff_buf.grow((size_t)(nq + 1) * sizeof(int))) return BAL_E_OOM;
+  hipMemsetAsync(s.h_qcnt.p, 0, (nq + 1) * sizeof(int), s.stream);
+  hipMemsetAsync(s.flags.p, 0, sizeof(int), s.stream);
+  if (nq > 0)
+    hipLaunchKernelGGL(k_lbvh_count, dim3(blocks_for(nq, 128)), dim3(128), 0, s.stream, A, T, s.h_qcnt.as<int>(),
+                       s.flags.as<int>());
+  int *fl = s.pin.as<int>() + 1024;
+  hipMemcpyAsync(fl, s.flags.p, sizeof(int), hipMemcpyDeviceToHost, s.stream);
+  int P = scan_exclusive(s, s.h_qcnt.as<int>(), qoff_buf.as<int>(), nq + 1);  // synchronises
+  if (P < 0) return BAL_E_OOM;
+  if (*fl & 4) return BAL_E_CAPACITY;  // descent stack overflow (not reachable for 64-bit keys)
+  if (out_buf.grow((size_t)(P + 1) * sizeof(int))) return BAL_E_OOM;
+  if (nq > 0 && P > 0)
+    hipLaunchKernelGGL(k_lbvh_write, dim3(blocks_for(nq, 128)), dim3(128), 0, s.stream, A, T, qoff_buf.as<int>(),
+                       out_buf.as<int>());
+  *qoff_out_n = nq;
+  return P;
+}
+
 int build_candidates(Scene &s, PairList &out, const double *x, const double *p) {
   out.n = 0;
   if (s.nsv == 0 && s.nse == 0) return BAL_OK;
+  auto half = s.desc.broad_phase == BAL_BROAD_LBVH ? lbvh_half : hash_half;
   DBuf &qoff_pt = s.qoff_pt, &out_pt = s.out_pt;
   int nq_pt = 0, nq_ee = 0;
-  int Ppt = hash_half(s, 0, 1, x, p, &nq_pt, qoff_pt, out_pt);
+  int Ppt = half(s, 0, 1, x, p, &nq_pt, qoff_pt, out_pt);
   if (Ppt < 0) return Ppt;
   // emit PT pairs before the EE pass reuses the scratch
   if (grow_pairs(out, Ppt)) return BAL_E_OOM;
@@ -380,7 +665,7 @@ int build_candidates(Scene &s, PairList &out, const double *x, const double *p) 
                        out.key.as<uint64_t>());
   hipStreamSynchronize(s.stream);
   DBuf &qoff_ee = s.qoff_ee, &out_ee = s.out_ee;
-  int Pee = hash_half(s, 2, 2, x, p, &nq_ee, qoff_ee, out_ee);
+  int Pee = half(s, 2, 2, x, p, &nq_ee, qoff_ee, out_ee);
   if (Pee < 0) return Pee;
   int total = Ppt + Pee;
   if (Pee > 0) {

@@ -337,12 +337,84 @@ __device__ void rank_sort(int lo, int hi, int *__restrict__ key, int *__restrict
   __syncthreads();
 }
 
+// The same for (column, source) pairs in lexicographic order: the entries of
+// one column become adjacent, in source order (sources are distinct).
+__device__ void rank_sort2(int lo, int hi, int *__restrict__ col, int *__restrict__ src, int *sk, int *sp) {
+  const int m = hi - lo, lane = threadIdx.x;
+  if (m <= 1) return;
+  auto less = [](int c0, int s0, int c1, int s1) { return c0 < c1 || (c0 == c1 && s0 < s1); };
+  if (m > kRankSort) {
+    if (lane == 0)
+      for (int a = lo + 1; a < hi; ++a) {
+        const int c = col[a], v = src[a];
+        int b = a - 1;
+        while (b >= lo && less(c, v, col[b], src[b])) {
+          col[b + 1] = col[b];
+          src[b + 1] = src[b];
+          --b;
+        }
+        col[b + 1] = c;
+        src[b + 1] = v;
+      }
+    return;
+  }
+  for (int e = lane; e < m; e += blockDim.x) {
+    sk[e] = col[lo + e];
+    sp[e] = src[lo + e];
+  }
+  __syncthreads();
+  for (int e = lane; e < m; e += blockDim.x) {
+    const int c = sk[e], v = sp[e];
+    int r = 0;
+    for (int f = 0; f < m; ++f) r += less(sk[f], sp[f], c, v);
+    col[lo + r] = c;
+    src[lo + r] = v;
+  }
+  __syncthreads();
+}
+
 __global__ void k_contact_sort(const int *__restrict__ dptr, int *__restrict__ dsrc, const int *__restrict__ optr,
                                int *__restrict__ ocol, int *__restrict__ osrc) {
   __shared__ int sk[kRankSort], sp[kRankSort];
   const int i = blockIdx.x;
   rank_sort(dptr[i], dptr[i + 1], dsrc, nullptr, sk, sp);
-  rank_sort(optr[i], optr[i + 1], osrc, ocol, sk, sp);
+  rank_sort2(optr[i], optr[i + 1], ocol, osrc, sk, sp);
+}
+
+// Merged contact blocks: every row's off-diagonal contact sources with the
+// same column are summed (in source order, in FP64, rounded once to the
+// storage precision) into one block, so the products read one block per
+// distinct (row, column) instead of one per pair that touches it.
+__global__ void k_contact_merge_count(int N, const int *__restrict__ optr, const int *__restrict__ ocol,
+                                      int *__restrict__ mcnt) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  int c = 0;
+  for (int e = optr[i]; e < optr[i + 1]; ++e) c += (e == optr[i] || ocol[e] != ocol[e - 1]);
+  mcnt[i] = c;
+}
+
+template <typename MT>
+__global__ void k_contact_merge(int N, const int *__restrict__ optr, const int *__restrict__ ocol,
+                                const int *__restrict__ osrc, const MT *__restrict__ pblk,
+                                const int *__restrict__ mptr, int *__restrict__ mcol, MT *__restrict__ mblk) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  int m = mptr[i];
+  const int e1 = optr[i + 1];
+  for (int e = optr[i]; e < e1;) {
+    const int col = ocol[e];
+    double acc[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (; e < e1 && ocol[e] == col; ++e) {
+      const MT *b = pblk + (size_t)9 * osrc[e];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) acc[k] += (double)b[k];
+    }
+    mcol[m] = col;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) mblk[(size_t)9 * m + k] = (MT)acc[k];
+    ++m;
+  }
 }
 
 int build_contact_lists(Scene &s) {
@@ -371,6 +443,29 @@ int build_contact_lists(Scene &s) {
     if (N > 0)
       hipLaunchKernelGGL(k_contact_sort, dim3(N), dim3(64), 0, s.stream, s.cdiag_ptr.as<int>(), s.cdiag_src.as<int>(),
                          s.coff_ptr.as<int>(), s.coff_col.as<int>(), s.coff_src.as<int>());
+  }
+  // merged off-diagonal contact blocks (one per distinct row, column)
+  if (s.cm_ptr.grow((N + 1) * sizeof(int))) return BAL_E_OOM;
+  int *mcnt = s.ccount.as<int>();  // the counts above are consumed
+  hipMemsetAsync(mcnt, 0, (size_t)(N + 1) * sizeof(int), s.stream);
+  if (s.n_coff > 0 && N > 0)
+    hipLaunchKernelGGL(k_contact_merge_count, dim3(blocks_for(N, kBS)), dim3(kBS), 0, s.stream, N,
+                       s.coff_ptr.as<int>(), s.coff_col.as<int>(), mcnt);
+  s.n_cm = s.n_coff > 0 ? scan_exclusive(s, mcnt, s.cm_ptr.as<int>(), N + 1)
+                        : (hipMemsetAsync(s.cm_ptr.p, 0, (N + 1) * sizeof(int), s.stream), 0);
+  if (s.n_cm < 0) return BAL_E_OOM;
+  const size_t w = s.mixed ? 4 : 8;
+  if (s.cm_col.grow((size_t)(s.n_cm + 1) * sizeof(int)) || s.cm_blk.grow((size_t)(s.n_cm + 1) * 9 * w))
+    return BAL_E_OOM;
+  if (s.n_coff > 0 && N > 0) {
+    if (s.mixed)
+      hipLaunchKernelGGL((k_contact_merge<float>), dim3(blocks_for(N, kBS)), dim3(kBS), 0, s.stream, N,
+                         s.coff_ptr.as<int>(), s.coff_col.as<int>(), s.coff_src.as<int>(), s.pair_blk.as<float>(),
+                         s.cm_ptr.as<int>(), s.cm_col.as<int>(), s.cm_blk.as<float>());
+    else
+      hipLaunchKernelGGL((k_contact_merge<double>), dim3(blocks_for(N, kBS)), dim3(kBS), 0, s.stream, N,
+                         s.coff_ptr.as<int>(), s.coff_col.as<int>(), s.coff_src.as<int>(), s.pair_blk.as<double>(),
+                         s.cm_ptr.as<int>(), s.cm_col.as<int>(), s.cm_blk.as<double>());
   }
   return BAL_OK;
 }
@@ -546,7 +641,7 @@ struct BsrView {
   const int *up;        // transposed rows: pointer
   const int2 *ue;       // (row m, block position) of the blocks (m, j), m > j
   const MT *D;          // diagonal blocks
-  const int *cp, *cc, *cs;  // contact rows: pointer, column, pair-block source
+  const int *cp, *cc, *cs;  // contact rows: pointer, column of the merged blocks (cs unused)
   const MT *pblk;
   const int2 *ent;      // FP32 storage: per row, lower then transposed entries (operand, block)
   int ndummy;           // index of the closing dummy entry
@@ -555,8 +650,8 @@ struct BsrView {
 template <typename MT>
 static BsrView<MT> bsr_view(const Scene &s) {
   return BsrView<MT>{s.row_ptr.as<int>(), s.col_idx.as<int>(), static_cast<const MT *>(s.val.p), s.up_ptr.as<int>(),
-                     s.up_ent.as<int2>(), static_cast<const MT *>(s.Dblk.p), s.coff_ptr.as<int>(),
-                     s.coff_col.as<int>(), s.coff_src.as<int>(), static_cast<const MT *>(s.pair_blk.p),
+                     s.up_ent.as<int2>(), static_cast<const MT *>(s.Dblk.p), s.cm_ptr.as<int>(),
+                     s.cm_col.as<int>(), nullptr, static_cast<const MT *>(s.cm_blk.p),
                      s.ent.as<int2>(), 2 * s.nnzb};
 }
 
@@ -741,7 +836,7 @@ __device__ __forceinline__ void contact_rows(int c0, int c1, int g, const BsrVie
       on[u] = cu < c1;
       const int ce = on[u] ? cu : c;
       j[u] = B.cc[ce];
-      a[u] = B.pblk + (size_t)9 * B.cs[ce];
+      a[u] = B.pblk + (size_t)9 * ce;
     }
     MT blk[kC][9];
     VT w[kC][3];
@@ -814,7 +909,7 @@ __device__ __forceinline__ bool spmv_row_pre(int i, int g, const BsrView<MT> &B,
         const int j = B.cc[c];
         VT w0[3];
         v.load(j, w0);
-        if (!MASK || grp[j] == gi) blk_mv<MT, VT>(B.pblk + (size_t)9 * B.cs[c], w0, acc);
+        if (!MASK || grp[j] == gi) blk_mv<MT, VT>(B.pblk + (size_t)9 * c, w0, acc);
       }
     }
   }
@@ -870,7 +965,7 @@ void launch_spmv(Scene &s, const void *vin, void *vout, int masked) {
 double spmv_bytes(const Scene &s) {
   // the paper's symmetric storage: each off-diagonal pair of blocks once
   double w = s.mixed ? 4.0 : 8.0;
-  double nL = (double)s.nnzb, nC = 0.5 * (double)s.n_coff;
+  double nL = (double)s.nnzb, nC = 0.5 * (double)s.n_cm;
   double N = (double)s.N;
   return (nL + nC) * (9.0 * w + 4.0) + N * 9.0 * w + 4.0 * N + 3.0 * N * w + 3.0 * N * w;
 }

@@ -378,6 +378,53 @@ def chain_net_large(E_net=1e9):
     return chain_net(n_u=28, sphere_level=5, sphere_layers=4, n_steps=1, E_net=E_net)
 
 
+def open_box(lo, hi):
+    """Floor and four walls of an open box (an aquarium), inward-facing
+    triangles: 8 vertices, 10 triangles."""
+    pos, tris = box_mesh(lo, hi)
+    top = [t for t in range(12) if all(pos[v][1] >= hi[1] for v in tris[t])]
+    keep = np.array([t for t in range(12) if t not in top])
+    return pos, tris[keep]
+
+
+def tumbling_blocks(n_x=3, n_z=4, n_layers=5, cells=31, cell=0.01, gap=0.005, seed=0, E=5e5, nu=0.4,
+                    n_steps=1):
+    """The memory-limited scale-up workload: n_x * n_z * n_layers randomly
+    rotated blocks of cells^3 cells x 5 tets stacked in columns (each block
+    `gap` above the highest point of the one below, the lowest layer `gap`
+    above the floor) inside an open box.  The default, 60 blocks of 31^3
+    cells (8,936,700 tets, 1,966,080 vertices), stands in for the paper's
+    tumbling-T-rex scene (its Table of scenarios: 9M tets, E = 5e5, one step
+    of h = 1/30)."""
+    rng = np.random.default_rng(seed)
+    base, base_tets = tet_grid(cells, cells, cells, cell)
+    base = base - base.mean(axis=0)
+    nv = base.shape[0]
+    edge = cells * cell
+    pitch = 1.8 * edge
+    pos_all, tets_all = [], []
+    k = 0
+    for i in range(n_x):
+        for j in range(n_z):
+            top = 0.0
+            for _ in range(n_layers):
+                R = random_rotation(rng)
+                p = base @ R.T
+                p[:, 1] += top + gap - p[:, 1].min()
+                p[:, 0] += (i - 0.5 * (n_x - 1)) * pitch
+                p[:, 2] += (j - 0.5 * (n_z - 1)) * pitch
+                top = p[:, 1].max()
+                pos_all.append(p)
+                tets_all.append(base_tets + k * nv)
+                k += 1
+    pos = np.concatenate(pos_all)
+    tets = np.concatenate(tets_all)
+    half_x, half_z = 0.5 * n_x * pitch + 0.1, 0.5 * n_z * pitch + 0.1
+    obs_pos, obs_tris = open_box((-half_x, 0.0, -half_z), (half_x, pos[:, 1].max() + 1.0, half_z))
+    return _pack(f"tumbling_blocks_{k}x{cells}^3", pos, tets, E, nu, 1000.0, None, obs_pos, obs_tris,
+                 dt=1.0 / 30.0, dhat=1e-3, n_steps=n_steps)
+
+
 def spmv_grid(n=128, cell=0.01, seed=2, amplitude=0.1):
     """Large regular grid for the block-SpMV roofline (no contact).
 

@@ -17,13 +17,21 @@ def small_beam(obstacle=False):
     return sc
 
 
+# The steps here are converged far below the paper's 1e-4 so that the finite
+# differences resolve the gradients; a step whose line search meets the FP64
+# rounding floor of L before the 1e-9 test passes counts as converged when its
+# gradient is below 1e-5 of the initial one (accept_rtol; on the beams the
+# floor sits at 1e-8..5e-6).
+ACCEPT = 1e-5
+
+
 def compare_adjoint(sc, n_pre, tol):
     from paper_2407_00046_amd import Scene
-    g = Scene(sc, newton_rtol=1e-9, pcg_rtol=1e-12, max_newton=200)
-    o = OracleScene(sc, Params(newton_rtol=1e-9, max_newton=200))
+    g = Scene(sc, newton_rtol=1e-9, pcg_rtol=1e-12, max_newton=200, accept_rtol=ACCEPT)
+    o = OracleScene(sc, Params(newton_rtol=1e-9, max_newton=200, accept_rtol=ACCEPT))
     for _ in range(n_pre):
-        g.step(allow=(0, -7))
-        o.step()
+        g.step()
+        assert o.step()["converged"]
     x_t, v_t = g.get_state()
     n = o.n_body
     assert np.abs(x_t - o.x[:n]).max() < 1e-6
@@ -54,7 +62,7 @@ def test_rollout_gradient_matches_central_differences():
     from paper_2407_00046_amd import Scene
     from paper_2407_00046_amd.bal import BalRollout
     sc = small_beam()
-    g = Scene(sc, newton_rtol=1e-9, pcg_rtol=1e-12, max_newton=200)
+    g = Scene(sc, newton_rtol=1e-9, pcg_rtol=1e-12, max_newton=200, accept_rtol=ACCEPT)
     T, every = 4, 2
     n = sc["rest_pos"].shape[0]
     tip = np.nonzero(np.abs(sc["rest_pos"][:, 0] - sc["rest_pos"][:, 0].max()) < 1e-9)[0]
@@ -110,7 +118,8 @@ def test_beam_full_size_rollout_gradients(box):
         sc["obs_tris"] = np.zeros((0, 3), np.int32)
     T, every = 20, 5
     # a differentiable step map: fixed barrier stiffness and no augmentation set
-    g = Scene(sc, newton_rtol=1e-9, pcg_rtol=1e-12, max_newton=300, use_al=False, sigma_fixed=1e3)
+    g = Scene(sc, newton_rtol=1e-9, pcg_rtol=1e-12, max_newton=300, use_al=False, sigma_fixed=1e3,
+              accept_rtol=ACCEPT)
     pos = sc["rest_pos"]
     tip = np.nonzero(np.abs(pos[:, 0] - pos[:, 0].max()) < 1e-9)[0]
     ref = BalRollout.apply(torch.full((len(sc["youngs"]),), 1e6, dtype=torch.float64),
