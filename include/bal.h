@@ -282,6 +282,36 @@ int bal_candidates(bal_scene *s, const double *x_all, const double *p_all, int32
  * offset per row, one read of the input and one write of the output. */
 int bal_spmv_benchmark(bal_scene *s, int32_t n_reps, double *ms_per_launch, double *bytes);
 
+/* CCD step bound over caller-given pairs, no scene (Sec. 5.3 narrow phase,
+ * with the scene's rules): alpha_max = min(1, min_i tau_i) along x + t p,
+ * t in [0, 1], for pairs (kind[i] 0 point-triangle / 1 edge-edge,
+ * nodes[i][4] = p,a,b,c or a0,a1,b0,b1 indexing x and p) with barrier offset
+ * dhat and rule ccd_rule (bal_ccd_rule).  Every pointer is device memory of
+ * `device`: x, p [n_verts][3] float64, kind [n_pairs], nodes [n_pairs][4]
+ * int32, alpha_max one float64.  The call is asynchronous on `stream`
+ * (hipStream_t, NULL for the default stream); *alpha_max is written when the
+ * stream reaches it.  A node index outside [0, n_verts) or a kind other than
+ * 0/1 makes *alpha_max NaN.  Scratch: one float64 per 1024 pairs, allocated
+ * and freed on the stream (hipMallocAsync / hipFreeAsync).
+ * Returns BAL_E_INVALID_ARG for null pointers, negative sizes, dhat <= 0 or
+ * an unknown rule; BAL_E_OOM if the scratch cannot be allocated. */
+int bal_pairs_ccd_bound(int32_t device, const double *x, const double *p, int32_t n_verts, const int32_t *kind,
+                        const int32_t *nodes, int32_t n_pairs, double dhat, int32_t ccd_rule, double *alpha_max,
+                        void *stream);
+
+/* bal_pairs_ccd_bound for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * kernels and result, with the scratch in a file-scope device array of
+ * 2^16 float64 (512 KiB) that each GPU the library runs on holds until the
+ * process ends.  At most 2^26 pairs per call (BAL_E_CAPACITY beyond, before
+ * any GPU work).  Every call on one GPU shares that GPU's array: calls that
+ * overlap on one GPU (two streams, two host threads) race.  Nothing needs
+ * clearing between calls (each call writes every partial it reads).  Other
+ * errors as bal_pairs_ccd_bound. */
+int bal_pairs_ccd_bound_noalloc(int32_t device, const double *x, const double *p, int32_t n_verts,
+                                const int32_t *kind, const int32_t *nodes, int32_t n_pairs, double dhat,
+                                int32_t ccd_rule, double *alpha_max, void *stream);
+
 /* Streaming-bandwidth reference for the rooflines above: on device `device`,
  * times n_reps launches of a read of n_bytes (summed, so every load is used)
  * and of a copy of n_bytes into a second buffer; reports bytes moved per

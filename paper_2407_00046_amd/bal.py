@@ -101,6 +101,9 @@ bal_ccd_bound = _sig("bal_ccd_bound", C.c_int, _vp, _vp, _vp, _dp)
 bal_candidates = _sig("bal_candidates", C.c_int, _vp, _vp, _vp, C.c_int32, _vp, _vp, _vp, _ip)
 bal_spmv_benchmark = _sig("bal_spmv_benchmark", C.c_int, _vp, C.c_int32, _dp, _dp)
 bal_stream_benchmark = _sig("bal_stream_benchmark", C.c_int, C.c_int32, C.c_int64, C.c_int32, _dp, _dp)
+_pairs_args = (C.c_int32, _vp, _vp, C.c_int32, _vp, _vp, C.c_int32, C.c_double, C.c_int32, _vp, _vp)
+bal_pairs_ccd_bound = _sig("bal_pairs_ccd_bound", C.c_int, *_pairs_args)
+bal_pairs_ccd_bound_noalloc = _sig("bal_pairs_ccd_bound_noalloc", C.c_int, *_pairs_args)
 
 EXPORTED = [n for n in dir() if n.startswith("bal_") and callable(globals()[n])
             and n not in ("bal_scene_desc", "bal_step_stats", "bal_al_state")]

@@ -613,3 +613,156 @@ void launch_ccd(Scene &s, const PairList &pl, const double *x, const double *p, 
 
 }  // namespace bal
 
+// ------------------------------------------------- CCD bound over given pairs
+// Stateless step bound over pairs the caller supplies (no scene): pass 1 takes
+// four pairs per thread and writes one partial minimum of tau per block; pass
+// 2 folds the partials into alpha_max = min(1, min tau).  A node index outside
+// [0, n_verts) turns the result into NaN (no host round trip, so the whole
+// call stays asynchronous on the caller's stream).
+#include <cmath>
+#include <mutex>
+
+namespace bal {
+
+constexpr int kPairsPerThread = 4;
+constexpr int kPairBlock = 256;
+constexpr int kPairsPerBlock = kPairsPerThread * kPairBlock;
+// partials of the scratch-array entry point: one double per block of pass 1
+constexpr int kPairScratchDoubles = 1 << 16;  // 512 KiB per device
+constexpr long kPairsMaxNoAlloc = (long)kPairScratchDoubles * kPairsPerBlock;
+
+__global__ void __launch_bounds__(kPairBlock) k_pairs_toi_min(int n, int n_verts, const int *__restrict__ kind,
+                                                              const int4 *__restrict__ nodes,
+                                                              const double *__restrict__ x,
+                                                              const double *__restrict__ p, double dhat, int rule,
+                                                              double *__restrict__ part) {
+  __shared__ double red[kPairBlock / 64];
+  double m = 1.0;
+  const int base = blockIdx.x * kPairsPerBlock + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < kPairsPerThread; ++k) {
+    const int i = base + k * kPairBlock;
+    if (i < n) {
+      const int4 nd = nodes[i];
+      const bool ok = nd.x >= 0 && nd.x < n_verts && nd.y >= 0 && nd.y < n_verts && nd.z >= 0 && nd.z < n_verts &&
+                      nd.w >= 0 && nd.w < n_verts && (kind[i] == 0 || kind[i] == 1);
+      if (!ok) {
+        m = NAN;
+      } else {
+        v3 X0[4], P[4];
+        load_pair(x, nd, X0);
+        load_pair(p, nd, P);
+        const double t = pair_toi(kind[i], X0, P, dhat, rule);
+        m = (m != m) ? m : fmin(m, t);  // NaN sticks
+      }
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const double o = __shfl_down(m, off, 64);
+    m = (m != m || o != o) ? NAN : fmin(m, o);
+  }
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = red[0];
+    for (int w = 1; w < kPairBlock / 64; ++w) r = (r != r || red[w] != red[w]) ? NAN : fmin(r, red[w]);
+    part[blockIdx.x] = r;
+  }
+}
+
+__global__ void __launch_bounds__(1024) k_pairs_min_final(int nb, const double *__restrict__ part,
+                                                          double *__restrict__ out) {
+  __shared__ double red[16];
+  double m = 1.0;
+  for (int i = threadIdx.x; i < nb; i += 1024) {
+    const double v = part[i];
+    m = (m != m || v != v) ? NAN : fmin(m, v);
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const double o = __shfl_down(m, off, 64);
+    m = (m != m || o != o) ? NAN : fmin(m, o);
+  }
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = red[0];
+    for (int w = 1; w < 16; ++w) r = (r != r || red[w] != red[w]) ? NAN : fmin(r, red[w]);
+    *out = r;
+  }
+}
+
+static int pairs_args_ok(const double *x, const double *p, int32_t n_verts, const int32_t *kind,
+                         const int32_t *nodes, int32_t n_pairs, double dhat, int32_t rule, const double *out) {
+  if (!x || !p || !out || n_verts < 0 || n_pairs < 0 || !(dhat > 0.0) || !std::isfinite(dhat)) return 0;
+  if (n_pairs > 0 && (!kind || !nodes)) return 0;
+  return rule == BAL_CCD_PRINTED || rule == BAL_CCD_HALF_GAP || rule == BAL_CCD_LITERAL;
+}
+
+static void launch_pairs_ccd(const double *x, const double *p, int32_t n_verts, const int32_t *kind,
+                             const int32_t *nodes, int32_t n_pairs, double dhat, int32_t rule, double *part,
+                             double *alpha_max, hipStream_t st) {
+  const int nb = n_pairs > 0 ? (int)((n_pairs + kPairsPerBlock - 1) / kPairsPerBlock) : 0;
+  if (nb > 0)
+    hipLaunchKernelGGL(k_pairs_toi_min, dim3(nb), dim3(kPairBlock), 0, st, n_pairs, n_verts, kind,
+                       (const int4 *)nodes, x, p, dhat, rule, part);
+  hipLaunchKernelGGL(k_pairs_min_final, dim3(1), dim3(1024), 0, st, nb, part, alpha_max);
+}
+
+// The scratch of bal_pairs_ccd_bound_noalloc: file-scope device memory, one
+// copy per GPU.  Host code never passes this name to a kernel; it uses the
+// device address looked up once per device (pair_scratch_ptr).
+static __device__ __align__(256) double scratch[kPairScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device `dev` (looked up once).
+static int pair_scratch_ptr(int dev, double **out) {
+  if (dev < 0 || dev >= kMaxDevices) return BAL_E_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return BAL_E_HIP;
+    g_scratch_ptr[dev] = static_cast<double *>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return BAL_OK;
+}
+
+}  // namespace bal
+
+extern "C" {
+
+int bal_pairs_ccd_bound(int32_t device, const double *x, const double *p, int32_t n_verts, const int32_t *kind,
+                        const int32_t *nodes, int32_t n_pairs, double dhat, int32_t ccd_rule, double *alpha_max,
+                        void *stream) {
+  using namespace bal;
+  if (!pairs_args_ok(x, p, n_verts, kind, nodes, n_pairs, dhat, ccd_rule, alpha_max)) return BAL_E_INVALID_ARG;
+  if (hipSetDevice(device) != hipSuccess) return BAL_E_INVALID_ARG;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const size_t nb = n_pairs > 0 ? (size_t)((n_pairs + kPairsPerBlock - 1) / kPairsPerBlock) : 1;
+  void *part = nullptr;
+  if (hipMallocAsync(&part, nb * sizeof(double), st) != hipSuccess) return BAL_E_OOM;
+  launch_pairs_ccd(x, p, n_verts, kind, nodes, n_pairs, dhat, ccd_rule, static_cast<double *>(part), alpha_max, st);
+  int rc = hip_ok(hipGetLastError());
+  if (hipFreeAsync(part, st) != hipSuccess && rc == BAL_OK) rc = BAL_E_HIP;
+  return rc;
+}
+
+int bal_pairs_ccd_bound_noalloc(int32_t device, const double *x, const double *p, int32_t n_verts,
+                                const int32_t *kind, const int32_t *nodes, int32_t n_pairs, double dhat,
+                                int32_t ccd_rule, double *alpha_max, void *stream) {
+  using namespace bal;
+  if (!pairs_args_ok(x, p, n_verts, kind, nodes, n_pairs, dhat, ccd_rule, alpha_max)) return BAL_E_INVALID_ARG;
+  if ((long)n_pairs > kPairsMaxNoAlloc) return BAL_E_CAPACITY;
+  if (hipSetDevice(device) != hipSuccess) return BAL_E_INVALID_ARG;
+  double *part = nullptr;
+  int rc = pair_scratch_ptr(device, &part);
+  if (rc) return rc;
+  launch_pairs_ccd(x, p, n_verts, kind, nodes, n_pairs, dhat, ccd_rule, part, alpha_max,
+                   static_cast<hipStream_t>(stream));
+  return hip_ok(hipGetLastError());
+}
+
+}  // extern "C"
