@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <vector>
@@ -502,6 +503,11 @@ static int newton_solve(Scene &s, bal_step_stats *st, bool record) {
     }
     S.newton_iters = l + 1;
     S.grad_rel = e0 > 0.0 ? enorm / e0 : 0.0;
+    if (s.verbose && (l % 25 == 0 || conv)) {
+      std::fprintf(stderr, "[bal] Newton %d: |A| %d |A'| %d |e|/|e0| %.3e alpha_max %.3e alpha %.3e PCG %d (%.1f s)\n",
+                   l, n_active, s.n_aug, S.grad_rel, amax, alpha, it_g, since(t_start));
+      std::fflush(stderr);
+    }
     if (conv) {
       copy3(s, x, xtr);
       status = BAL_OK;
@@ -1064,6 +1070,9 @@ int bal_create_scene(const bal_scene_desc *desc, bal_scene **out) {
       d.fixed = fx.data();
     }
     h->s.perm_h = perm;
+    // BAL_VERBOSE=1 in the environment: one progress line per 25 Newton iterations on stderr
+    const char *vb = std::getenv("BAL_VERBOSE");
+    h->s.verbose = vb && vb[0] == '1';
     rc = build_scene(h->s, &d);
     if (!rc) rc = upload(h->s, h->s.perm_d, perm.data(), std::max(nb, 1));
     if (!rc && h->s.stage.grow(3 * (size_t)h->s.N * 8 + 8)) rc = BAL_E_OOM;

