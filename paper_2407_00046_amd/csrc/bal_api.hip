@@ -1096,13 +1096,13 @@ void bal_destroy_scene(bal_scene *h) {
                   &s.blk_src_ptr, &s.blk_src, &s.up_ptr, &s.up_ent, &s.ent, &s.perm_d, &s.stage, &s.sv, &s.st, &s.se, &s.x, &s.v, &s.x_t, &s.v_t, &s.y,
                   &s.xtrial, &s.dx, &s.tet_e, &s.tet_g, &s.tet_tr, &s.tet_blk, &s.val, &s.Dblk, &s.Dinv, &s.e_nodes,
                   &s.group, &s.grad, &s.grad_b, &s.uni_flag, &s.uni_aug, &s.pair_e, &s.pair_g, &s.pair_tr,
-                  &s.pair_blk, &s.cdiag_ptr, &s.cdiag_src, &s.coff_ptr, &s.coff_col, &s.coff_src, &s.cm_ptr, &s.cm_col, &s.cm_blk, &s.ccount,
+                  &s.pair_blk, &s.cdiag_ptr, &s.cdiag_src, &s.coff_ptr, &s.coff_col, &s.coff_src, &s.cm_ptr, &s.cm_col, &s.cm_blk, &s.cm_head, &s.cm_ridx, &s.ccount,
                   &s.cfill, &s.aug_kind, &s.aug_a, &s.aug_b, &s.aug_nodes, &s.aug_key, &s.aug_mu, &s.aug_s,
                   &s.aug_d, &s.aug_e, &s.aug_tmp_mu, &s.aug_tmp_s, &s.fr, &s.fr_e, &s.hb_lo, &s.hb_hi, &s.hq_lo, &s.hq_hi,
                   &s.h_cnt, &s.h_off, &s.h_key, &s.h_prim, &s.h_bcnt, &s.h_bstart, &s.h_bfill, &s.h_skey,
                   &s.h_sprim, &s.h_large, &s.h_nlarge, &s.h_qcnt, &s.h_lcnt, &s.h_qoff, &s.h_out, &s.qoff_pt, &s.out_pt,
                   &s.qoff_ee, &s.out_ee, &s.lb_part, &s.lb_key, &s.lb_key2, &s.lb_tmp, &s.lb_prim, &s.lb_child,
-                  &s.lb_parent, &s.lb_lparent, &s.lb_arrive, &s.lb_ibox, &s.r, &s.z, &s.pv, &s.pv2, &s.q, &s.pcg_ctl, &s.warm_ctl, &s.partial, &s.counter,
+                  &s.lb_parent, &s.lb_lparent, &s.lb_arrive, &s.lb_ibox, &s.h_sorted_pt, &s.h_sorted_ee, &s.r, &s.z, &s.pv, &s.pv2, &s.q, &s.pcg_ctl, &s.warm_ctl, &s.partial, &s.counter,
                   &s.scan_tmp, &s.red_out, &s.flags, &s.node_e, &s.cand_e, &s.mask, &s.mask_off, &s.tau, &s.rhs, &s.psweep};
   for (DBuf *b : bufs) b->release();
   PairList *pls[] = {&s.cand, &s.cand2, &s.uni, &s.augtmp};

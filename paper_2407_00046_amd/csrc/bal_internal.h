@@ -70,6 +70,7 @@ struct Scene {
   DBuf fr, fr_e;  // friction frame per union pair: lam, beta[4], n[3] (8 doubles); friction energies
   DBuf cdiag_ptr, cdiag_src, coff_ptr, coff_col, coff_src, ccount, cfill;
   DBuf cm_ptr, cm_col, cm_blk;  // merged off-diagonal contact blocks per row (one per distinct column)
+  DBuf cm_head, cm_ridx;        // run flags and run indices of the sorted off-diagonal entries
   int n_cdiag = 0, n_coff = 0, n_cm = 0;
   // augmentation set A' (sorted by key)
   int n_aug = 0;
@@ -82,6 +83,7 @@ struct Scene {
       h_large, h_nlarge, h_qcnt, h_lcnt, h_qoff, h_out, qoff_pt, out_pt, qoff_ee, out_ee;
   // LBVH scratch
   DBuf lb_part, lb_key, lb_key2, lb_tmp, lb_prim, lb_child, lb_parent, lb_lparent, lb_arrive, lb_ibox;
+  DBuf h_sorted_pt, h_sorted_ee;  // candidate keys of each half in canonical order
   // PCG
   DBuf ent;  // FP32 storage: per row its lower then transposed entries (operand, block), one dummy at the end
   DBuf r, z, pv, pv2, q, pcg_ctl, warm_ctl, partial, counter, scan_tmp, red_out, flags;

@@ -230,14 +230,14 @@ __global__ void k_query_count(QueryArgs A, int *lcnt, int *qcnt) {
 
 // Same traversal; each lane writes at the query's offset plus the counts of
 // the lanes before it.  The segment is sorted by the emit pass.
-__global__ void k_query_write(QueryArgs A, const int *lcnt, const int *qoff, int *outb) {
+__global__ void k_query_write(QueryArgs A, const int *lcnt, const int *qoff, uint64_t *outb) {
   int gid = blockIdx.x * blockDim.x + threadIdx.x;
   int q = gid / kQG, lane = gid % kQG;
   if (q >= A.nq) return;
   int o = qoff[q];
   const int *lc = lcnt + (size_t)q * kQG;
   for (int k = 0; k < lane; ++k) o += lc[k];
-  visit_query(A, q, lane, [&](int t) { outb[o++] = t; });
+  visit_query(A, q, lane, [&](int t) { outb[o++] = ((uint64_t)q << 32) | (uint32_t)t; });
 }
 
 // Queries whose box is tested directly against every entry.
@@ -255,30 +255,23 @@ __global__ void k_large_flag(int n, const Box *ebox, double ih, uint8_t *fl) {
   fl[i] = box_cells(b.lo, b.hi, ih) > (double)kLargeCells ? 1 : 0;
 }
 
-// Sorts each query's segment (insertion sort: segments are short) and
-// writes the pairs in canonical order.
-__global__ void k_emit_pairs(int nq, int kind, const int *qoff, int *outb, const int *sv, const int *st,
-                             const int *se, int base, int *okind, int *oa, int *ob, int4 *onodes, uint64_t *okey) {
-  int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= nq) return;
-  const int lo = qoff[q], hi = qoff[q + 1];
-  for (int a = lo + 1; a < hi; ++a) {
-    int v = outb[a], b = a - 1;
-    while (b >= lo && outb[b] > v) { outb[b + 1] = outb[b]; --b; }
-    outb[b + 1] = v;
-  }
-  for (int k = lo; k < hi; ++k) {
-    int t = outb[k];
-    int o = base + k;
-    okind[o] = kind;
-    oa[o] = q;
-    ob[o] = t;
-    int4 nd;
-    if (kind == 0) nd = make_int4(sv[q], st[3 * t], st[3 * t + 1], st[3 * t + 2]);
-    else nd = make_int4(se[2 * q], se[2 * q + 1], se[2 * t], se[2 * t + 1]);
-    onodes[o] = nd;
-    okey[o] = ((uint64_t)kind << 62) | ((uint64_t)q << 31) | (uint64_t)t;
-  }
+// Pairs from their (query, partner) keys, already radix-sorted into the
+// canonical (query, partner) order: one thread per pair.
+__global__ void k_emit_sorted(int P, int kind, const uint64_t *__restrict__ keys, const int *sv, const int *st,
+                              const int *se, int base, int *okind, int *oa, int *ob, int4 *onodes, uint64_t *okey) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= P) return;
+  const uint64_t key = keys[k];
+  const int q = (int)(key >> 32), t = (int)(uint32_t)key;
+  const int o = base + k;
+  okind[o] = kind;
+  oa[o] = q;
+  ob[o] = t;
+  int4 nd;
+  if (kind == 0) nd = make_int4(sv[q], st[3 * t], st[3 * t + 1], st[3 * t + 2]);
+  else nd = make_int4(se[2 * q], se[2 * q + 1], se[2 * t], se[2 * t + 1]);
+  onodes[o] = nd;
+  okey[o] = ((uint64_t)kind << 62) | ((uint64_t)q << 31) | (uint64_t)t;
 }
 
 static int grow_pairs(PairList &pl, int n) {
@@ -291,8 +284,8 @@ static int grow_pairs(PairList &pl, int n) {
 }
 
 // One half of the pass (point-triangle or edge-edge); returns the pair count
-// (negative on error) and leaves per-query offsets / partner lists in
-// qoff_buf / out_buf for k_emit_pairs.  Two host synchronisations: the entry
+// (negative on error) and leaves per-query offsets in qoff_buf and the
+// (query, partner) keys, grouped by query, in out_buf.  Two host synchronisations: the entry
 // count (with the large-entry and large-query counts of the work bound) and
 // the pair count.
 static int hash_half(Scene &s, int qtype, int etype, const double *x, const double *p, int *qoff_out_n,
@@ -358,10 +351,10 @@ static int hash_half(Scene &s, int qtype, int etype, const double *x, const doub
                        s.h_lcnt.as<int>(), s.h_qcnt.as<int>());
   int P = scan_exclusive(s, s.h_qcnt.as<int>(), qoff_buf.as<int>(), nq + 1);  // synchronises
   if (P < 0) return BAL_E_OOM;
-  if (out_buf.grow((size_t)(P + 1) * sizeof(int))) return BAL_E_OOM;
+  if (out_buf.grow((size_t)(P + 1) * sizeof(uint64_t))) return BAL_E_OOM;
   if (nq > 0 && P > 0)
     hipLaunchKernelGGL(k_query_write, dim3(blocks_for(qthreads, kHB)), dim3(kHB), 0, s.stream, A,
-                       s.h_lcnt.as<int>(), qoff_buf.as<int>(), out_buf.as<int>());
+                       s.h_lcnt.as<int>(), qoff_buf.as<int>(), out_buf.as<uint64_t>());
   *qoff_out_n = nq;
   return P;
 }
@@ -583,11 +576,11 @@ __global__ void k_lbvh_count(QueryArgs A, LbvhView T, int *qcnt, int *flags) {
   qcnt[q] = c;
 }
 
-__global__ void k_lbvh_write(QueryArgs A, LbvhView T, const int *qoff, int *outb) {
+__global__ void k_lbvh_write(QueryArgs A, LbvhView T, const int *qoff, uint64_t *outb) {
   int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= A.nq) return;
   int o = qoff[q];
-  lbvh_visit(A, T, q, [&](int t) { outb[o++] = t; });
+  lbvh_visit(A, T, q, [&](int t) { outb[o++] = ((uint64_t)q << 32) | (uint32_t)t; });
 }
 
 static int lbvh_half(Scene &s, int qtype, int etype, const double *x, const double *p, int *qoff_out_n,
@@ -640,47 +633,61 @@ static int lbvh_half(Scene &s, int qtype, int etype, const double *x, const doub
   int P = scan_exclusive(s, s.h_qcnt.as<int>(), qoff_buf.as<int>(), nq + 1);  // synchronises
   if (P < 0) return BAL_E_OOM;
   if (*fl & 4) return BAL_E_CAPACITY;  // descent stack overflow (not reachable for 64-bit keys)
-  if (out_buf.grow((size_t)(P + 1) * sizeof(int))) return BAL_E_OOM;
+  if (out_buf.grow((size_t)(P + 1) * sizeof(uint64_t))) return BAL_E_OOM;
   if (nq > 0 && P > 0)
     hipLaunchKernelGGL(k_lbvh_write, dim3(blocks_for(nq, 128)), dim3(128), 0, s.stream, A, T, qoff_buf.as<int>(),
-                       out_buf.as<int>());
+                       out_buf.as<uint64_t>());
   *qoff_out_n = nq;
   return P;
+}
+
+static int bits_for(int n) {
+  int b = 1;
+  while (b < 31 && (1 << b) < n) ++b;
+  return b;
+}
+
+// The half's keys radix-sorted into (query, partner) order (query in bits
+// 32.., partner in bits 0..31: only the bits in use are sorted), in `sorted`.
+static int sort_half(Scene &s, int P, int nq, DBuf &keys, DBuf &sorted) {
+  if (P <= 0) return BAL_OK;
+  if (sorted.grow((size_t)P * sizeof(uint64_t))) return BAL_E_OOM;
+  const int end_bit = 32 + bits_for(nq + 1);
+  size_t tmp = 0;
+  if (hipcub::DeviceRadixSort::SortKeys(nullptr, tmp, keys.as<uint64_t>(), sorted.as<uint64_t>(), P, 0, end_bit,
+                                        s.stream) != hipSuccess)
+    return BAL_E_HIP;
+  if (s.lb_tmp.grow(tmp + 16)) return BAL_E_OOM;
+  if (hipcub::DeviceRadixSort::SortKeys(s.lb_tmp.p, tmp, keys.as<uint64_t>(), sorted.as<uint64_t>(), P, 0, end_bit,
+                                        s.stream) != hipSuccess)
+    return BAL_E_HIP;
+  return BAL_OK;
 }
 
 int build_candidates(Scene &s, PairList &out, const double *x, const double *p) {
   out.n = 0;
   if (s.nsv == 0 && s.nse == 0) return BAL_OK;
   auto half = s.desc.broad_phase == BAL_BROAD_LBVH ? lbvh_half : hash_half;
-  DBuf &qoff_pt = s.qoff_pt, &out_pt = s.out_pt;
   int nq_pt = 0, nq_ee = 0;
-  int Ppt = half(s, 0, 1, x, p, &nq_pt, qoff_pt, out_pt);
+  const int Ppt = half(s, 0, 1, x, p, &nq_pt, s.qoff_pt, s.out_pt);
   if (Ppt < 0) return Ppt;
-  // emit PT pairs before the EE pass reuses the scratch
-  if (grow_pairs(out, Ppt)) return BAL_E_OOM;
-  if (nq_pt > 0 && Ppt > 0)
-    hipLaunchKernelGGL(k_emit_pairs, dim3(blocks_for(nq_pt, kHB)), dim3(kHB), 0, s.stream, nq_pt, 0,
-                       qoff_pt.as<int>(), out_pt.as<int>(), s.sv.as<int>(), s.st.as<int>(), s.se.as<int>(), 0,
-                       out.kind.as<int>(), out.a.as<int>(), out.b.as<int>(), out.nodes.as<int4>(),
-                       out.key.as<uint64_t>());
-  hipStreamSynchronize(s.stream);
-  DBuf &qoff_ee = s.qoff_ee, &out_ee = s.out_ee;
-  int Pee = half(s, 2, 2, x, p, &nq_ee, qoff_ee, out_ee);
+  int rc = sort_half(s, Ppt, nq_pt, s.out_pt, s.h_sorted_pt);
+  if (rc) return rc;
+  const int Pee = half(s, 2, 2, x, p, &nq_ee, s.qoff_ee, s.out_ee);
   if (Pee < 0) return Pee;
-  int total = Ppt + Pee;
-  if (Pee > 0) {
-    // grow keeps nothing: re-emit the PT half after growing
-    if (grow_pairs(out, total)) return BAL_E_OOM;
-    if (nq_pt > 0 && Ppt > 0)
-      hipLaunchKernelGGL(k_emit_pairs, dim3(blocks_for(nq_pt, kHB)), dim3(kHB), 0, s.stream, nq_pt, 0,
-                         qoff_pt.as<int>(), out_pt.as<int>(), s.sv.as<int>(), s.st.as<int>(), s.se.as<int>(), 0,
-                         out.kind.as<int>(), out.a.as<int>(), out.b.as<int>(), out.nodes.as<int4>(),
-                         out.key.as<uint64_t>());
-    hipLaunchKernelGGL(k_emit_pairs, dim3(blocks_for(nq_ee, kHB)), dim3(kHB), 0, s.stream, nq_ee, 1,
-                       qoff_ee.as<int>(), out_ee.as<int>(), s.sv.as<int>(), s.st.as<int>(), s.se.as<int>(), Ppt,
+  if ((rc = sort_half(s, Pee, nq_ee, s.out_ee, s.h_sorted_ee))) return rc;
+  const int total = Ppt + Pee;
+  if (grow_pairs(out, total)) return BAL_E_OOM;
+  if (Ppt > 0)
+    hipLaunchKernelGGL(k_emit_sorted, dim3(blocks_for(Ppt, kHB)), dim3(kHB), 0, s.stream, Ppt, 0,
+                       s.h_sorted_pt.as<uint64_t>(), s.sv.as<int>(), s.st.as<int>(), s.se.as<int>(), 0,
                        out.kind.as<int>(), out.a.as<int>(), out.b.as<int>(), out.nodes.as<int4>(),
                        out.key.as<uint64_t>());
-  }
+  if (Pee > 0)
+    hipLaunchKernelGGL(k_emit_sorted, dim3(blocks_for(Pee, kHB)), dim3(kHB), 0, s.stream, Pee, 1,
+                       s.h_sorted_ee.as<uint64_t>(), s.sv.as<int>(), s.st.as<int>(), s.se.as<int>(), Ppt,
+                       out.kind.as<int>(), out.a.as<int>(), out.b.as<int>(), out.nodes.as<int4>(),
+                       out.key.as<uint64_t>());
   out.n = total;
   return BAL_OK;
 }

@@ -384,37 +384,43 @@ __global__ void k_contact_sort(const int *__restrict__ dptr, int *__restrict__ d
 // Merged contact blocks: every row's off-diagonal contact sources with the
 // same column are summed (in source order, in FP64, rounded once to the
 // storage precision) into one block, so the products read one block per
-// distinct (row, column) instead of one per pair that touches it.
-__global__ void k_contact_merge_count(int N, const int *__restrict__ optr, const int *__restrict__ ocol,
-                                      int *__restrict__ mcnt) {
+// distinct (row, column) instead of one per pair that touches it.  A run is
+// a maximal stretch of one row's sorted entries with one column: its first
+// entry is flagged, the flags are scanned into run indices, and one thread
+// per run sums it.
+__global__ void k_run_rows(int N, const int *__restrict__ optr, int *__restrict__ head) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  int c = 0;
-  for (int e = optr[i]; e < optr[i + 1]; ++e) c += (e == optr[i] || ocol[e] != ocol[e - 1]);
-  mcnt[i] = c;
+  if (i < N && optr[i] < optr[i + 1]) head[optr[i]] = 1;
+}
+
+__global__ void k_run_cols(int n, const int *__restrict__ ocol, int *__restrict__ head) {
+  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n && e > 0 && ocol[e] != ocol[e - 1]) head[e] = 1;
 }
 
 template <typename MT>
-__global__ void k_contact_merge(int N, const int *__restrict__ optr, const int *__restrict__ ocol,
-                                const int *__restrict__ osrc, const MT *__restrict__ pblk,
-                                const int *__restrict__ mptr, int *__restrict__ mcol, MT *__restrict__ mblk) {
+__global__ void k_merge_runs(int n, const int *__restrict__ head, const int *__restrict__ ridx,
+                             const int *__restrict__ ocol, const int *__restrict__ osrc, const MT *__restrict__ pblk,
+                             int *__restrict__ mcol, MT *__restrict__ mblk) {
+  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n || !head[e]) return;
+  double acc[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int f = e;
+  do {
+    const MT *b = pblk + (size_t)9 * osrc[f];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) acc[k] += (double)b[k];
+    ++f;
+  } while (f < n && !head[f]);
+  const int m = ridx[e];
+  mcol[m] = ocol[e];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) mblk[(size_t)9 * m + k] = (MT)acc[k];
+}
+
+__global__ void k_run_ptr(int N, const int *__restrict__ optr, const int *__restrict__ ridx, int *__restrict__ mptr) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  int m = mptr[i];
-  const int e1 = optr[i + 1];
-  for (int e = optr[i]; e < e1;) {
-    const int col = ocol[e];
-    double acc[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (; e < e1 && ocol[e] == col; ++e) {
-      const MT *b = pblk + (size_t)9 * osrc[e];
-#pragma unroll
-      for (int k = 0; k < 9; ++k) acc[k] += (double)b[k];
-    }
-    mcol[m] = col;
-#pragma unroll
-    for (int k = 0; k < 9; ++k) mblk[(size_t)9 * m + k] = (MT)acc[k];
-    ++m;
-  }
+  if (i <= N) mptr[i] = ridx[optr[i]];
 }
 
 int build_contact_lists(Scene &s) {
@@ -445,27 +451,32 @@ int build_contact_lists(Scene &s) {
                          s.coff_ptr.as<int>(), s.coff_col.as<int>(), s.coff_src.as<int>());
   }
   // merged off-diagonal contact blocks (one per distinct row, column)
-  if (s.cm_ptr.grow((N + 1) * sizeof(int))) return BAL_E_OOM;
-  int *mcnt = s.ccount.as<int>();  // the counts above are consumed
-  hipMemsetAsync(mcnt, 0, (size_t)(N + 1) * sizeof(int), s.stream);
-  if (s.n_coff > 0 && N > 0)
-    hipLaunchKernelGGL(k_contact_merge_count, dim3(blocks_for(N, kBS)), dim3(kBS), 0, s.stream, N,
-                       s.coff_ptr.as<int>(), s.coff_col.as<int>(), mcnt);
-  s.n_cm = s.n_coff > 0 ? scan_exclusive(s, mcnt, s.cm_ptr.as<int>(), N + 1)
-                        : (hipMemsetAsync(s.cm_ptr.p, 0, (N + 1) * sizeof(int), s.stream), 0);
+  const int nc = s.n_coff;
+  if (s.cm_ptr.grow((N + 1) * sizeof(int)) || s.cm_head.grow((size_t)(nc + 1) * sizeof(int)) ||
+      s.cm_ridx.grow((size_t)(nc + 1) * sizeof(int)))
+    return BAL_E_OOM;
+  int *head = s.cm_head.as<int>(), *ridx = s.cm_ridx.as<int>();
+  hipMemsetAsync(head, 0, (size_t)(nc + 1) * sizeof(int), s.stream);
+  if (nc > 0) {
+    hipLaunchKernelGGL(k_run_rows, dim3(blocks_for(N, kBS)), dim3(kBS), 0, s.stream, N, s.coff_ptr.as<int>(), head);
+    hipLaunchKernelGGL(k_run_cols, dim3(blocks_for(nc, kBS)), dim3(kBS), 0, s.stream, nc, s.coff_col.as<int>(), head);
+  }
+  s.n_cm = scan_exclusive(s, head, ridx, nc + 1);
   if (s.n_cm < 0) return BAL_E_OOM;
+  hipLaunchKernelGGL(k_run_ptr, dim3(blocks_for(N + 1, kBS)), dim3(kBS), 0, s.stream, N, s.coff_ptr.as<int>(), ridx,
+                     s.cm_ptr.as<int>());
   const size_t w = s.mixed ? 4 : 8;
   if (s.cm_col.grow((size_t)(s.n_cm + 1) * sizeof(int)) || s.cm_blk.grow((size_t)(s.n_cm + 1) * 9 * w))
     return BAL_E_OOM;
-  if (s.n_coff > 0 && N > 0) {
+  if (nc > 0) {
     if (s.mixed)
-      hipLaunchKernelGGL((k_contact_merge<float>), dim3(blocks_for(N, kBS)), dim3(kBS), 0, s.stream, N,
-                         s.coff_ptr.as<int>(), s.coff_col.as<int>(), s.coff_src.as<int>(), s.pair_blk.as<float>(),
-                         s.cm_ptr.as<int>(), s.cm_col.as<int>(), s.cm_blk.as<float>());
+      hipLaunchKernelGGL((k_merge_runs<float>), dim3(blocks_for(nc, kBS)), dim3(kBS), 0, s.stream, nc, head, ridx,
+                         s.coff_col.as<int>(), s.coff_src.as<int>(), s.pair_blk.as<float>(), s.cm_col.as<int>(),
+                         s.cm_blk.as<float>());
     else
-      hipLaunchKernelGGL((k_contact_merge<double>), dim3(blocks_for(N, kBS)), dim3(kBS), 0, s.stream, N,
-                         s.coff_ptr.as<int>(), s.coff_col.as<int>(), s.coff_src.as<int>(), s.pair_blk.as<double>(),
-                         s.cm_ptr.as<int>(), s.cm_col.as<int>(), s.cm_blk.as<double>());
+      hipLaunchKernelGGL((k_merge_runs<double>), dim3(blocks_for(nc, kBS)), dim3(kBS), 0, s.stream, nc, head, ridx,
+                         s.coff_col.as<int>(), s.coff_src.as<int>(), s.pair_blk.as<double>(), s.cm_col.as<int>(),
+                         s.cm_blk.as<double>());
   }
   return BAL_OK;
 }
