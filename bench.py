@@ -381,6 +381,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-r1", action="store_true", help="skip the 128^3-grid SpMV roofline")
     ap.add_argument("--ccd-rule", default="printed", choices=["printed", "half_gap", "literal"])
+    ap.add_argument("--broad-phase", default="hash", choices=["hash", "lbvh"])
     ap.add_argument("--large", action="store_true")
     ap.add_argument("--ablations", action="store_true")
     ap.add_argument("--scale", action="store_true")
@@ -409,11 +410,11 @@ def main():
     if args.ablations:
         mode_ablations(sc, args.steps, stream, args.ccd_rule)
         return
-    fp64, states = run_fp64(sc, args.steps, args.warmup, stream, ccd_rule=args.ccd_rule)
+    fp64, states = run_fp64(sc, args.steps, args.warmup, stream, ccd_rule=args.ccd_rule, broad_phase=args.broad_phase)
     print(f"[bench] fp64: {fp64['s_per_step']:.3f} s/step", flush=True)
     mixed = None
     if not args.no_mixed:
-        mixed = run_mixed_from(sc, states, args.steps, stream, ccd_rule=args.ccd_rule)
+        mixed = run_mixed_from(sc, states, args.steps, stream, ccd_rule=args.ccd_rule, broad_phase=args.broad_phase)
         print(f"[bench] mixed: {mixed['s_per_step']:.3f} s/step, max one-step eps_x vs fp64 "
               f"{mixed['eps_x_vs_fp64_max']:.2e}", flush=True)
     r1 = None
@@ -432,7 +433,7 @@ def main():
         dtype="f64", data="synthetic",
         config=dict(workload=sc["name"], n_tets=int(sc["tets"].shape[0]), n_verts=int(sc["rest_pos"].shape[0]),
                     workload_steps=int(sc["n_steps"]), precision="fp64", dt=sc["dt"], dhat=sc["dhat"],
-                    ccd_rule=args.ccd_rule, **TOL),
+                    ccd_rule=args.ccd_rule, broad_phase=args.broad_phase, **TOL),
         roofline=roofline_of(fp64, "k_cg_dir_spmv<double, double>"), cpu_baseline=cpu, spmv_hbm=r1, fp64=fp64,
         mixed=mixed,
         mixed_speedup=(fp64["s_per_step"] / mixed["s_per_step"]) if mixed else None,
