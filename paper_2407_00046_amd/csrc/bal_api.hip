@@ -788,7 +788,7 @@ static int build_scene(Scene &s, const bal_scene_desc *d) {
   s.nsrc = (int)bsrc.size();
   // transposed index: row j lists the stored blocks (i, j), ascending i
   std::vector<int> upp(N + 1, 0);
-  std::vector<int2> upe(std::max(s.nnzb, 1));
+  std::vector<int2> upe(s.nnzb + 1);
   for (int k = 0; k < s.nnzb; ++k) upp[ci[k] + 1]++;
   for (int i = 0; i < N; ++i) upp[i + 1] += upp[i];
   {
@@ -796,6 +796,10 @@ static int build_scene(Scene &s, const bal_scene_desc *d) {
     for (int i = 0; i < N; ++i)
       for (int k = rp[i]; k < rp[i + 1]; ++k) upe[fill[ci[k]]++] = make_int2(i, k);
   }
+  // pad entries closing both lists (lower: column 0; transposed: operand 0
+  // and the spare block), read by the branch-free FP64 walk in place of an
+  // entry of the other list or past the row's end
+  upe[s.nnzb] = make_int2(0, s.nnzb);
   // FP32 storage also keeps one entry list per row: (column, block) of its
   // lower blocks, then (row, block) of its transposed ones; a dummy entry
   // (operand 0, the spare block) closes the list
@@ -809,6 +813,7 @@ static int build_scene(Scene &s, const bal_scene_desc *d) {
     }
     entl[o] = make_int2(0, s.nnzb);
   }
+  ci.push_back(0);
   // device uploads
   std::vector<int4> tet4(T);
   for (int t = 0; t < T; ++t) tet4[t] = make_int4(d->tets[4 * t], d->tets[4 * t + 1], d->tets[4 * t + 2], d->tets[4 * t + 3]);
@@ -842,6 +847,8 @@ static int build_scene(Scene &s, const bal_scene_desc *d) {
   s.pin.bytes = 1 << 16;
   hipMemsetAsync(s.flags.p, 0, 64, s.stream);
   hipMemsetAsync(s.counter.p, 0, 64, s.stream);
+  // the spare block (read by lanes past a row's end, whose product is dropped)
+  hipMemsetAsync(static_cast<char *>(s.val.p) + (size_t)s.nnzb * 9 * w, 0, 9 * w, s.stream);
   // empty contact lists
   if ((rc = build_contact_lists(s))) return rc;
   // initial state
@@ -1100,7 +1107,7 @@ void bal_destroy_scene(bal_scene *h) {
                   &s.cfill, &s.aug_kind, &s.aug_a, &s.aug_b, &s.aug_nodes, &s.aug_key, &s.aug_mu, &s.aug_s,
                   &s.aug_d, &s.aug_e, &s.aug_tmp_mu, &s.aug_tmp_s, &s.fr, &s.fr_e, &s.hb_lo, &s.hb_hi, &s.hq_lo, &s.hq_hi,
                   &s.h_cnt, &s.h_off, &s.h_key, &s.h_prim, &s.h_bcnt, &s.h_bstart, &s.h_bfill, &s.h_skey,
-                  &s.h_sprim, &s.h_large, &s.h_nlarge, &s.h_qcnt, &s.h_lcnt, &s.h_qoff, &s.h_out, &s.qoff_pt, &s.out_pt,
+                  &s.h_sprim, &s.h_large, &s.h_nlarge, &s.h_qcnt, &s.h_lcnt, &s.h_slots, &s.h_qoff, &s.h_out, &s.qoff_pt, &s.out_pt,
                   &s.qoff_ee, &s.out_ee, &s.lb_part, &s.lb_key, &s.lb_key2, &s.lb_tmp, &s.lb_prim, &s.lb_child,
                   &s.lb_parent, &s.lb_lparent, &s.lb_arrive, &s.lb_ibox, &s.h_sorted_pt, &s.h_sorted_ee, &s.r, &s.z, &s.pv, &s.pv2, &s.q, &s.pcg_ctl, &s.warm_ctl, &s.partial, &s.counter,
                   &s.scan_tmp, &s.red_out, &s.flags, &s.node_e, &s.cand_e, &s.mask, &s.mask_off, &s.tau, &s.rhs, &s.psweep};

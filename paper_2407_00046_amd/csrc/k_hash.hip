@@ -24,6 +24,7 @@ constexpr long kLargeCells = 64;
 constexpr long kQueryCells = 4096;
 constexpr int kOff = 1 << 20;
 constexpr int kQG = 8;  // lanes per query (a power of two dividing the wave)
+constexpr int kQSlots = 8;  // keys a query lane keeps from the counting traversal
 // Bound on the box tests of one pass (direct tests of large entries and of
 // large queries); beyond it the pass reports BAL_E_CAPACITY and the caller
 // shortens the sweep.
@@ -215,17 +216,38 @@ __device__ void visit_query(const QueryArgs &A, int q, int lane, F emit) {
 }
 
 // One thread per (query, lane); the kQG lanes of a query are consecutive
-// lanes of one wave.  Writes the lane's count and the query's total.
-__global__ void k_query_count(QueryArgs A, int *lcnt, int *qcnt) {
+// lanes of one wave.  Writes the lane's count and the query's total, and
+// keeps the lane's first kQSlots keys in its own slots.  A lane with more
+// raises the overflow flag (a plain store of 1) and the pass traverses
+// again with k_query_write; otherwise k_query_compact moves the slots into
+// place, so that one traversal serves both count and write.
+__global__ void k_query_count_keep(QueryArgs A, int *lcnt, int *qcnt, uint64_t *slots, int *ovf) {
   int gid = blockIdx.x * blockDim.x + threadIdx.x;
   int q = gid / kQG, lane = gid % kQG;
   if (q >= A.nq) return;  // whole groups leave together
+  uint64_t *mine = slots + (size_t)gid * kQSlots;
   int c = 0;
-  visit_query(A, q, lane, [&](int) { ++c; });
+  visit_query(A, q, lane, [&](int t) {
+    if (c < kQSlots) mine[c] = ((uint64_t)q << 32) | (uint32_t)t;
+    ++c;
+  });
   lcnt[gid] = c;
+  if (c > kQSlots) *ovf = 1;
 #pragma unroll
   for (int m = kQG / 2; m > 0; m >>= 1) c += __shfl_xor(c, m, kQG);
   if (lane == 0) qcnt[q] = c;
+}
+
+__global__ void k_query_compact(int nq, const int *lcnt, const int *qoff, const uint64_t *slots, uint64_t *outb) {
+  int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  int q = gid / kQG, lane = gid % kQG;
+  if (q >= nq) return;
+  int o = qoff[q];
+  const int *lc = lcnt + (size_t)q * kQG;
+  for (int k = 0; k < lane; ++k) o += lc[k];
+  const int c = lc[lane];  // <= kQSlots: no lane overflowed
+  const uint64_t *mine = slots + (size_t)gid * kQSlots;
+  for (int m = 0; m < c; ++m) outb[o + m] = mine[m];
 }
 
 // Same traversal; each lane writes at the query's offset plus the counts of
@@ -296,12 +318,13 @@ static int hash_half(Scene &s, int qtype, int etype, const double *x, const doub
   double infl = s.desc.dhat;
   if (s.hb_lo.grow((size_t)(ne + 1) * sizeof(Box)) || s.h_cnt.grow((size_t)(ne + 1) * sizeof(int)) ||
       s.h_off.grow((size_t)(ne + 1) * sizeof(int)) || s.h_large.grow((size_t)(ne + 1) * sizeof(int)) ||
-      s.h_nlarge.grow(2 * sizeof(int)) || s.hq_lo.grow((size_t)(nq + 1) * sizeof(uint8_t)) ||
-      s.h_lcnt.grow(((size_t)nq * kQG + 1) * sizeof(int)))
+      s.h_nlarge.grow(3 * sizeof(int)) || s.hq_lo.grow((size_t)(nq + 1) * sizeof(uint8_t)) ||
+      s.h_lcnt.grow(((size_t)nq * kQG + 1) * sizeof(int)) ||
+      s.h_slots.grow(((size_t)nq * kQG * kQSlots + 1) * sizeof(uint64_t)))
     return BAL_E_OOM;
   Box *ebox = s.hb_lo.as<Box>();
-  int *nlarge_d = s.h_nlarge.as<int>();  // [0] large entries, [1] large queries
-  hipMemsetAsync(nlarge_d, 0, 2 * sizeof(int), s.stream);
+  int *nlarge_d = s.h_nlarge.as<int>();  // [0] large entries, [1] large queries, [2] slot overflow
+  hipMemsetAsync(nlarge_d, 0, 3 * sizeof(int), s.stream);
   if (ne > 0)
     hipLaunchKernelGGL(k_entry_boxes, dim3(blocks_for(ne, kHB)), dim3(kHB), 0, s.stream, ne, etype, s.sv.as<int>(),
                        s.st.as<int>(), s.se.as<int>(), x, p, infl, ih, ebox, s.h_cnt.as<int>(), s.h_large.as<int>(),
@@ -347,14 +370,20 @@ static int hash_half(Scene &s, int qtype, int etype, const double *x, const doub
   hipMemsetAsync(s.h_qcnt.p, 0, (nq + 1) * sizeof(int), s.stream);
   const int qthreads = nq * kQG;  // nq * kQG < 2^31: nq is a surface count
   if (nq > 0)
-    hipLaunchKernelGGL(k_query_count, dim3(blocks_for(qthreads, kHB)), dim3(kHB), 0, s.stream, A,
-                       s.h_lcnt.as<int>(), s.h_qcnt.as<int>());
+    hipLaunchKernelGGL(k_query_count_keep, dim3(blocks_for(qthreads, kHB)), dim3(kHB), 0, s.stream, A,
+                       s.h_lcnt.as<int>(), s.h_qcnt.as<int>(), s.h_slots.as<uint64_t>(), nlarge_d + 2);
+  hipMemcpyAsync(hn + 2, nlarge_d + 2, sizeof(int), hipMemcpyDeviceToHost, s.stream);
   int P = scan_exclusive(s, s.h_qcnt.as<int>(), qoff_buf.as<int>(), nq + 1);  // synchronises
   if (P < 0) return BAL_E_OOM;
   if (out_buf.grow((size_t)(P + 1) * sizeof(uint64_t))) return BAL_E_OOM;
-  if (nq > 0 && P > 0)
-    hipLaunchKernelGGL(k_query_write, dim3(blocks_for(qthreads, kHB)), dim3(kHB), 0, s.stream, A,
-                       s.h_lcnt.as<int>(), qoff_buf.as<int>(), out_buf.as<uint64_t>());
+  if (nq > 0 && P > 0) {
+    if (hn[2])  // some lane found more than its slots hold: traverse again
+      hipLaunchKernelGGL(k_query_write, dim3(blocks_for(qthreads, kHB)), dim3(kHB), 0, s.stream, A,
+                         s.h_lcnt.as<int>(), qoff_buf.as<int>(), out_buf.as<uint64_t>());
+    else
+      hipLaunchKernelGGL(k_query_compact, dim3(blocks_for(qthreads, kHB)), dim3(kHB), 0, s.stream, nq,
+                         s.h_lcnt.as<int>(), qoff_buf.as<int>(), s.h_slots.as<uint64_t>(), out_buf.as<uint64_t>());
+  }
   *qoff_out_n = nq;
   return P;
 }

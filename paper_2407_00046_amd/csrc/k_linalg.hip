@@ -656,6 +656,7 @@ struct BsrView {
   const MT *pblk;
   const int2 *ent;      // FP32 storage: per row, lower then transposed entries (operand, block)
   int ndummy;           // index of the closing dummy entry
+  int npad;             // index of the pad entries closing ci and ue (and of the spare block)
 };
 
 template <typename MT>
@@ -663,7 +664,7 @@ static BsrView<MT> bsr_view(const Scene &s) {
   return BsrView<MT>{s.row_ptr.as<int>(), s.col_idx.as<int>(), static_cast<const MT *>(s.val.p), s.up_ptr.as<int>(),
                      s.up_ent.as<int2>(), static_cast<const MT *>(s.Dblk.p), s.cm_ptr.as<int>(),
                      s.cm_col.as<int>(), nullptr, static_cast<const MT *>(s.cm_blk.p),
-                     s.ent.as<int2>(), 2 * s.nnzb};
+                     s.ent.as<int2>(), 2 * s.nnzb, s.nnzb};
 }
 
 template <typename MT>
@@ -746,12 +747,16 @@ __device__ __forceinline__ void blk_mtv(const MT *__restrict__ a, const VT *w, V
 // product launch has its own copy of this loop, which also issues the first
 // pass's raw operand entries before its scalars are known.)
 constexpr int kU = 3;
+// entries per pass of the PCG product's branch-free FP64 walk: its batch's
+// loads are all in flight together, and two per pass keep the registers
+// within three waves per SIMD (three per pass need 204)
+constexpr int kUSplit = 2;
 
-template <typename MT>
+template <typename MT, int U = kU>
 struct RowBatch {
-  int j[kU], k[kU];
-  bool tr[kU], on[kU];
-  MT a[kU][9];
+  int j[U], k[U];
+  bool tr[U], on[U];
+  MT a[U][9];
 };
 
 template <typename MT>
@@ -794,11 +799,11 @@ __device__ __forceinline__ void row_fetch(int i, int t, int l0, int nl, int u0, 
 template <typename MT>
 constexpr bool kUnifiedWalk = sizeof(MT) == 4;
 
-template <typename MT>
+template <typename MT, int U>
 __device__ __forceinline__ void row_fetch_unified(int t, int ep, int nl, int nt, const BsrView<MT> &B,
-                                                  RowBatch<MT> &rb) {
+                                                  RowBatch<MT, U> &rb) {
 #pragma unroll
-  for (int u = 0; u < kU; ++u) {
+  for (int u = 0; u < U; ++u) {
     const int tt = t + u * kG;
     rb.on[u] = tt < nt;
     rb.tr[u] = tt >= nl;
@@ -807,7 +812,38 @@ __device__ __forceinline__ void row_fetch_unified(int t, int ep, int nl, int nt,
     rb.k[u] = e.y;
   }
 #pragma unroll
-  for (int u = 0; u < kU; ++u) {
+  for (int u = 0; u < U; ++u) {
+    const MT *src = B.val + (size_t)9 * rb.k[u];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) rb.a[u][c] = src[c];
+  }
+}
+
+// FP64 storage, branch-free: each of a lane's kU entries reads both of its
+// candidate index entries, the lower list's (l0 + tt while tt < nl, else
+// the pad entry) and the transposed list's (u0 + tt - nl while nl <= tt <
+// nt, else the pad entry), and keeps the one its position selects; past
+// the row's end that is the transposed pad (operand 0, the spare block),
+// whose product the caller drops by a select.  With no branch among them,
+// a batch's index loads, then its block loads, stay in flight together
+// (the predicated walk waited for every earlier load at each branch join).
+template <typename MT, int U>
+__device__ __forceinline__ void row_fetch_split(int t, int l0, int nl, int u0, int nt, const BsrView<MT> &B,
+                                                RowBatch<MT, U> &rb) {
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int tt = t + u * kG;
+    rb.on[u] = tt < nt;
+    rb.tr[u] = tt >= nl;
+    const int kl = tt < nl ? l0 + tt : B.npad;
+    const int ku = rb.tr[u] && rb.on[u] ? u0 + tt - nl : B.npad;
+    const int cj = B.ci[kl];
+    const int2 e = B.ue[ku];
+    rb.j[u] = rb.tr[u] ? e.x : cj;
+    rb.k[u] = rb.tr[u] ? e.y : kl;
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
     const MT *src = B.val + (size_t)9 * rb.k[u];
 #pragma unroll
     for (int c = 0; c < 9; ++c) rb.a[u][c] = src[c];
@@ -826,6 +862,25 @@ __device__ __forceinline__ void blk_sel(const MT *a, const VT *w, bool tr, bool 
   acc[0] += on ? (tr ? t0 : d0) : (VT)0;
   acc[1] += on ? (tr ? t1 : d1) : (VT)0;
   acc[2] += on ? (tr ? t2 : d2) : (VT)0;
+}
+
+// The same with the block's transpose taken by selecting its elements
+// (FP64 storage: one product instead of two keeps the registers of a
+// batch's blocks and operands, all in flight together, within three waves
+// per SIMD)
+template <typename MT, typename VT>
+__device__ __forceinline__ void blk_sel_t(const MT *a, const VT *w, bool tr, bool on, VT *acc) {
+  MT b[9];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) b[3 * r + c] = r == c ? a[3 * r + c] : (tr ? a[3 * c + r] : a[3 * r + c]);
+  const VT d0 = (VT)b[0] * w[0] + (VT)b[1] * w[1] + (VT)b[2] * w[2];
+  const VT d1 = (VT)b[3] * w[0] + (VT)b[4] * w[1] + (VT)b[5] * w[2];
+  const VT d2 = (VT)b[6] * w[0] + (VT)b[7] * w[1] + (VT)b[8] * w[2];
+  acc[0] += on ? d0 : (VT)0;
+  acc[1] += on ? d1 : (VT)0;
+  acc[2] += on ? d2 : (VT)0;
 }
 
 // The row's contact blocks (per-pair block grids read through the row's
@@ -877,7 +932,7 @@ __device__ __forceinline__ bool spmv_row_pre(int i, int g, const BsrView<MT> &B,
     c0 = B.cp[i];
     c1 = B.cp[i + 1];
     if (MASK) gi = grp[i];
-    if constexpr (kUnifiedWalk<MT>) row_fetch_unified<MT>(g, l0 + u0, nl, nt, B, rb);
+    if constexpr (kUnifiedWalk<MT>) row_fetch_unified<MT, kU>(g, l0 + u0, nl, nt, B, rb);
     else row_fetch<MT>(i, g, l0, nl, u0, nt, B, rb);
     if (g == 0) {
 #pragma unroll
@@ -908,7 +963,7 @@ __device__ __forceinline__ bool spmv_row_pre(int i, int g, const BsrView<MT> &B,
       }
       t += kU * kG;
       if (t >= nt) break;
-      if constexpr (kUnifiedWalk<MT>) row_fetch_unified<MT>(t, l0 + u0, nl, nt, B, rb);
+      if constexpr (kUnifiedWalk<MT>) row_fetch_unified<MT, kU>(t, l0 + u0, nl, nt, B, rb);
       else row_fetch<MT>(i, t, l0, nl, u0, nt, B, rb);
     }
     if constexpr (kUnifiedWalk<MT>) {
@@ -1210,39 +1265,36 @@ __global__ __launch_bounds__(kBS) void k_cg_dir_spmv(int N, int k, BsrView<MT> B
                                                      const VT *__restrict__ p_old, VT *__restrict__ p_new,
                                                      VT *__restrict__ q, CgCtl *ctl, const double *part, int nb,
                                                      const double *part_pq_prev, double *part_pq) {
-  if (ctl->stop) return;
-  const CgSlot &prev = ctl->slot[(k - 1) & 1];
+  const int tile = xcd_tile();
+  const long t = (long)tile * blockDim.x + threadIdx.x;
+  const int i = t / kG < N ? (int)(t / kG) : -1, g = (int)(t % kG);
+  // the row's extents depend on nothing in the control block: their loads
+  // are issued with the control block's, all before the first wait (one
+  // exit test over every control word, so that no load waits for another)
+  // (lanes past the last row read row 0's and ignore them: no branch, so
+  // no copy of a loaded register that would wait for it)
+  const int ir = i >= 0 ? i : 0;
+  const int rp0 = B.rp[ir], rp1 = B.rp[ir + 1], up0 = B.up[ir], up1 = B.up[ir + 1];
+  const int c0 = i >= 0 ? B.cp[ir] : 0, c1 = i >= 0 ? B.cp[ir + 1] : 0;
+  const CgSlot prev = ctl->slot[(k - 1) & 1];
+  const int stop = ctl->stop, cur_done = ctl->slot[k & 1].done;
   const bool first = prev.it < 0;
-  if (first ? ctl->slot[k & 1].done : prev.done) return;
+  if (stop | (first ? cur_done : prev.done)) return;
+  const int l0 = rp0, nl = rp1 - rp0, u0 = up0, nt = nl + up1 - up0;
   const double *src[3] = {part, part + nb, part_pq_prev};
   const int cnt[3] = {nb, nb, (int)gridDim.x};
   double pv[3][4];
   if (!first) sums_load<3>(src, cnt, pv);
-  const int tile = xcd_tile();
-  const long t = (long)tile * blockDim.x + threadIdx.x;
-  const int i = t / kG < N ? (int)(t / kG) : -1, g = (int)(t % kG);
   VecDir<VT> dir{z, first ? z : p_old, 0.0};  // p_0 = z_0: beta = 0 must not meet an unset buffer
   VT acc[3] = {(VT)0, (VT)0, (VT)0};
-  int l0 = 0, nl = 0, u0 = 0, nt = 0, c0 = 0, c1 = 0;
-  RowBatch<MT> rb;
-  MT dblk[9];
-  VT zr[kU][3], pr[kU][3];
+  constexpr int U = kUnifiedWalk<MT> ? kU : kUSplit;
+  RowBatch<MT, U> rb;
+  VT zr[U][3], pr[U][3];
   if (i >= 0) {
-    l0 = B.rp[i];
-    nl = B.rp[i + 1] - l0;
-    u0 = B.up[i];
-    nt = nl + B.up[i + 1] - u0;
-    c0 = B.cp[i];
-    c1 = B.cp[i + 1];
-    if constexpr (kUnifiedWalk<MT>) row_fetch_unified<MT>(g, l0 + u0, nl, nt, B, rb);
-    else row_fetch<MT>(i, g, l0, nl, u0, nt, B, rb);
-    if (g == 0) {
+    if constexpr (kUnifiedWalk<MT>) row_fetch_unified<MT, U>(g, l0 + u0, nl, nt, B, rb);
+    else row_fetch_split<MT, U>(g, l0, nl, u0, nt, B, rb);
 #pragma unroll
-      for (int c = 0; c < 9; ++c) dblk[c] = B.D[(size_t)9 * i + c];
-    }
-#pragma unroll
-    for (int u = 0; u < kU; ++u)
-      if (kUnifiedWalk<MT> || rb.on[u]) dir.raw(rb.j[u], zr[u], pr[u]);
+    for (int u = 0; u < U; ++u) dir.raw(rb.j[u], zr[u], pr[u]);
   }
   if (!first) {
     // the state after iteration k and beta_k
@@ -1275,30 +1327,20 @@ __global__ __launch_bounds__(kBS) void k_cg_dir_spmv(int N, int k, BsrView<MT> B
   }
   if (i >= 0) {
     for (int tt = g;;) {
-      VT w[kU][3];
-      if constexpr (kUnifiedWalk<MT>) {
+      VT w[U][3];
 #pragma unroll
-        for (int u = 0; u < kU; ++u) dir.form(zr[u], pr[u], w[u]);
+      for (int u = 0; u < U; ++u) dir.form(zr[u], pr[u], w[u]);
 #pragma unroll
-        for (int u = 0; u < kU; ++u) blk_sel<MT, VT>(rb.a[u], w[u], rb.tr[u], rb.on[u], acc);
-      } else {
-#pragma unroll
-        for (int u = 0; u < kU; ++u)
-          if (rb.on[u]) dir.form(zr[u], pr[u], w[u]);
-#pragma unroll
-        for (int u = 0; u < kU; ++u)
-          if (rb.on[u]) {
-            if (rb.tr[u]) blk_mtv<MT, VT>(rb.a[u], w[u], acc);
-            else blk_mv<MT, VT>(rb.a[u], w[u], acc);
-          }
+      for (int u = 0; u < U; ++u) {
+        if constexpr (kUnifiedWalk<MT>) blk_sel<MT, VT>(rb.a[u], w[u], rb.tr[u], rb.on[u], acc);
+        else blk_sel_t<MT, VT>(rb.a[u], w[u], rb.tr[u], rb.on[u], acc);
       }
-      tt += kU * kG;
+      tt += U * kG;
       if (tt >= nt) break;
-      if constexpr (kUnifiedWalk<MT>) row_fetch_unified<MT>(tt, l0 + u0, nl, nt, B, rb);
-      else row_fetch<MT>(i, tt, l0, nl, u0, nt, B, rb);
+      if constexpr (kUnifiedWalk<MT>) row_fetch_unified<MT, U>(tt, l0 + u0, nl, nt, B, rb);
+      else row_fetch_split<MT, U>(tt, l0, nl, u0, nt, B, rb);
 #pragma unroll
-      for (int u = 0; u < kU; ++u)
-        if (kUnifiedWalk<MT> || rb.on[u]) dir.raw(rb.j[u], zr[u], pr[u]);
+      for (int u = 0; u < U; ++u) dir.raw(rb.j[u], zr[u], pr[u]);
     }
     contact_rows<MT, VT, false>(c0, c1, g, B, nullptr, 0, dir, acc);
   }
@@ -1309,7 +1351,12 @@ __global__ __launch_bounds__(kBS) void k_cg_dir_spmv(int N, int k, BsrView<MT> B
   double vals[1] = {0.0};
   int bin = -1;
   if (i >= 0 && g == 0) {
+    // the diagonal block and the row's own operand entries are read here,
+    // in one round, rather than held in registers through the walk
     VT own[3];
+    MT dblk[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) dblk[c] = B.D[(size_t)9 * i + c];
     dir.load(i, own);
     blk_mv<MT, VT>(dblk, own, acc);
 #pragma unroll
@@ -1331,15 +1378,16 @@ __global__ __launch_bounds__(kBS) void k_cg_update(int N, int k, const uint8_t *
                                                    const VT *__restrict__ q, double *__restrict__ x,
                                                    double *__restrict__ r, VT *__restrict__ z, const CgCtl *ctl,
                                                    const double *part_pq, int nb_pq, double *part) {
-  const CgSlot &s = ctl->slot[k & 1];
-  if (ctl->stop || s.done) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  // the p.q partials are loaded first, then the node's operands, which are
-  // in flight while the partials are summed
-  const bool act = i < N && fr[i];
+  // the node's operands (whether or not the node is free) are loaded with
+  // its free flag and the control block, and are in flight while the p.q
+  // partials are summed
+  const bool in = i < N;
   double pv[3] = {0.0, 0.0, 0.0}, qv[3] = {0.0, 0.0, 0.0}, xv[3] = {0.0, 0.0, 0.0}, rv[3] = {0.0, 0.0, 0.0};
   MT d[9];
-  if (act) {
+  bool act = false;
+  if (in) {
+    act = fr[i] != 0;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       pv[c] = (double)p[3 * i + c];
@@ -1350,11 +1398,14 @@ __global__ __launch_bounds__(kBS) void k_cg_update(int N, int k, const uint8_t *
 #pragma unroll
     for (int c = 0; c < 9; ++c) d[c] = Dinv[(size_t)9 * i + c];
   }
+  const int stop = ctl->stop, done = ctl->slot[k & 1].done;
+  const double rz = ctl->slot[k & 1].rz;
+  if (stop || done) return;
   double pq;
   const double *src[1] = {part_pq};
   const int cnt[1] = {nb_pq};
   block_sums<1>(src, cnt, &pq);
-  const double al = pq > 0.0 ? s.rz / pq : 0.0;  // a breakdown is recorded by the next launch
+  const double al = pq > 0.0 ? rz / pq : 0.0;  // a breakdown is recorded by the next launch
   double vals[2] = {0.0, 0.0};
   int bin = -1;
   if (act) {

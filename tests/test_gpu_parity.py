@@ -241,8 +241,11 @@ def candidate_keys(kind, nodes):
 @pytest.mark.parametrize("case", ["tiny_cube", "two_boxes"])
 def test_candidates_equal_box_overlap_set(case, broad):
     """Either broad phase (spatial hash, or the paper's LBVH) returns exactly
-    the box-overlap candidate set, each pair once, at rest and along a swept
-    displacement."""
+    the box-overlap candidate set, each pair once, at rest and along swept
+    displacements.  At rest every hash query lane finds a few partners and
+    the keys it keeps in its slots are compacted into place; the 6 cm sweep
+    spans whole cubes, so lanes find more partners than their slots hold and
+    the pass traverses a second time to write them."""
     if case == "tiny_cube":
         sc = scenes.tiny_cube()
         o, x, _, _, _ = contact_state(sc)
@@ -255,7 +258,7 @@ def test_candidates_equal_box_overlap_set(case, broad):
     sv, st, se = g.surface()
     free = np.concatenate([sc["fixed"] == 0, np.zeros(x.shape[0] - nb, bool)])
     rng = np.random.default_rng(9)
-    for scale in (0.0, 2e-3, 2e-2):
+    for scale in (0.0, 2e-3, 2e-2, 6e-2):
         p = None
         if scale > 0:
             p = np.zeros_like(x)
