@@ -1107,7 +1107,7 @@ void bal_destroy_scene(bal_scene *h) {
                   &s.cfill, &s.aug_kind, &s.aug_a, &s.aug_b, &s.aug_nodes, &s.aug_key, &s.aug_mu, &s.aug_s,
                   &s.aug_d, &s.aug_e, &s.aug_tmp_mu, &s.aug_tmp_s, &s.fr, &s.fr_e, &s.hb_lo, &s.hb_hi, &s.hq_lo, &s.hq_hi,
                   &s.h_cnt, &s.h_off, &s.h_key, &s.h_prim, &s.h_bcnt, &s.h_bstart, &s.h_bfill, &s.h_skey,
-                  &s.h_sprim, &s.h_large, &s.h_nlarge, &s.h_qcnt, &s.h_lcnt, &s.h_slots, &s.h_qoff, &s.h_out, &s.qoff_pt, &s.out_pt,
+                  &s.h_sprim, &s.h_large, &s.h_nlarge, &s.h_qcnt, &s.h_lcnt, &s.h_slots, &s.h_plen, &s.h_qoff, &s.h_out, &s.qoff_pt, &s.out_pt,
                   &s.qoff_ee, &s.out_ee, &s.lb_part, &s.lb_key, &s.lb_key2, &s.lb_tmp, &s.lb_prim, &s.lb_child,
                   &s.lb_parent, &s.lb_lparent, &s.lb_arrive, &s.lb_ibox, &s.h_sorted_pt, &s.h_sorted_ee, &s.r, &s.z, &s.pv, &s.pv2, &s.q, &s.pcg_ctl, &s.warm_ctl, &s.partial, &s.counter,
                   &s.scan_tmp, &s.red_out, &s.flags, &s.node_e, &s.cand_e, &s.mask, &s.mask_off, &s.tau, &s.rhs, &s.psweep};

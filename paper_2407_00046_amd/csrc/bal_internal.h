@@ -80,7 +80,7 @@ struct Scene {
   bool sigma_set = false;
   // hash scratch
   DBuf hb_lo, hb_hi, hq_lo, hq_hi, h_cnt, h_off, h_key, h_prim, h_bcnt, h_bstart, h_bfill, h_skey, h_sprim,
-      h_large, h_nlarge, h_qcnt, h_lcnt, h_slots, h_qoff, h_out, qoff_pt, out_pt, qoff_ee, out_ee;
+      h_large, h_nlarge, h_qcnt, h_lcnt, h_slots, h_plen, h_qoff, h_out, qoff_pt, out_pt, qoff_ee, out_ee;
   // LBVH scratch
   DBuf lb_part, lb_key, lb_key2, lb_tmp, lb_prim, lb_child, lb_parent, lb_lparent, lb_arrive, lb_ibox;
   DBuf h_sorted_pt, h_sorted_ee;  // candidate keys of each half in canonical order

@@ -18,10 +18,13 @@ struct ElemBasis {
   double Q[12];
 };
 
-template <typename MT>
+// MODE is a template argument: the energy and gradient launches (line
+// search, gradient) then get registers for what they compute, not the
+// Hessian's eigen-solve footprint, and run at full occupancy
+template <typename MT, int MODE>
 __global__ __launch_bounds__(128) void k_elements(int T, const int4 *__restrict__ tets,
                                                   const TetConst *__restrict__ tc, const double *__restrict__ x,
-                                                  int mode, int project, ElemBasis eb, double *__restrict__ tet_e,
+                                                  int project, ElemBasis eb, double *__restrict__ tet_e,
                                                   double *__restrict__ tet_g, MT *__restrict__ tet_blk,
                                                   double *__restrict__ tet_tr, int *__restrict__ flags) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -45,7 +48,7 @@ __global__ __launch_bounds__(128) void k_elements(int T, const int4 *__restrict_
   double I1 = dot(F0, F0) + dot(F1, F1) + dot(F2, F2);
   double lj = log(J);
   tet_e[t] = 0.5 * k.Vmu * (I1 - 3.0) - k.Vmu * lj + 0.5 * k.Vlam * lj * lj;
-  if (mode == EM_ENERGY) return;
+  if constexpr (MODE == EM_ENERGY) return;
   double Vc = k.Vlam * lj - k.Vmu;
   v3 gu[3];
 #pragma unroll
@@ -59,7 +62,7 @@ __global__ __launch_bounds__(128) void k_elements(int T, const int4 *__restrict_
     gt[4 + 3 * q] = gu[q].y;
     gt[5 + 3 * q] = gu[q].z;
   }
-  if (mode == EM_GRAD) return;
+  if constexpr (MODE == EM_GRAD) return;
   const double *L = eb.L;
   v3 d[3];
 #pragma unroll
@@ -100,20 +103,28 @@ __global__ __launch_bounds__(128) void k_elements(int T, const int4 *__restrict_
   }
 }
 
+template <typename MT, int MODE>
+static void launch_elements_t(Scene &s, const double *x, int project, const ElemBasis &eb) {
+  dim3 grid(blocks_for(s.T, 128)), block(128);
+  hipLaunchKernelGGL((k_elements<MT, MODE>), grid, block, 0, s.stream, s.T, s.tets.as<int4>(), s.tc.as<TetConst>(),
+                     x, project, eb, s.tet_e.as<double>(), s.tet_g.as<double>(), static_cast<MT *>(s.tet_blk.p),
+                     s.tet_tr.as<double>(), s.flags.as<int>());
+}
+
+template <typename MT>
+static void launch_elements_m(Scene &s, const double *x, int mode, int project, const ElemBasis &eb) {
+  if (mode == EM_ENERGY) launch_elements_t<MT, EM_ENERGY>(s, x, project, eb);
+  else if (mode == EM_GRAD) launch_elements_t<MT, EM_GRAD>(s, x, project, eb);
+  else launch_elements_t<MT, EM_HESS>(s, x, project, eb);
+}
+
 void launch_elements(Scene &s, const double *x, int mode, int project) {
   ElemBasis eb;
   for (int i = 0; i < 9; ++i) eb.L[i] = s.Lel[i];
   for (int i = 0; i < 12; ++i) eb.Q[i] = s.Qel[i];
-  dim3 grid(blocks_for(s.T, 128)), block(128);
   if (s.T == 0) return;
-  if (s.mixed)
-    hipLaunchKernelGGL(k_elements<float>, grid, block, 0, s.stream, s.T, s.tets.as<int4>(), s.tc.as<TetConst>(), x,
-                       mode, project, eb, s.tet_e.as<double>(), s.tet_g.as<double>(), s.tet_blk.as<float>(),
-                       s.tet_tr.as<double>(), s.flags.as<int>());
-  else
-    hipLaunchKernelGGL(k_elements<double>, grid, block, 0, s.stream, s.T, s.tets.as<int4>(), s.tc.as<TetConst>(), x,
-                       mode, project, eb, s.tet_e.as<double>(), s.tet_g.as<double>(), s.tet_blk.as<double>(),
-                       s.tet_tr.as<double>(), s.flags.as<int>());
+  if (s.mixed) launch_elements_m<float>(s, x, mode, project, eb);
+  else launch_elements_m<double>(s, x, mode, project, eb);
 }
 
 }  // namespace bal

@@ -310,11 +310,11 @@ static int grow_pairs(PairList &pl, int n) {
 // (query, partner) keys, grouped by query, in out_buf.  Two host synchronisations: the entry
 // count (with the large-entry and large-query counts of the work bound) and
 // the pair count.
-static int hash_half(Scene &s, int qtype, int etype, const double *x, const double *p, int *qoff_out_n,
-                     DBuf &qoff_buf, DBuf &out_buf) {
+static int hash_half(Scene &s, int qtype, int etype, const double *x, const double *p, double cell,
+                     int *qoff_out_n, DBuf &qoff_buf, DBuf &out_buf) {
   int nq = qtype == 0 ? s.nsv : s.nse;
   int ne = etype == 1 ? s.nst : s.nse;
-  double ih = 1.0 / s.cell;
+  double ih = 1.0 / cell;
   double infl = s.desc.dhat;
   if (s.hb_lo.grow((size_t)(ne + 1) * sizeof(Box)) || s.h_cnt.grow((size_t)(ne + 1) * sizeof(int)) ||
       s.h_off.grow((size_t)(ne + 1) * sizeof(int)) || s.h_large.grow((size_t)(ne + 1) * sizeof(int)) ||
@@ -612,8 +612,8 @@ __global__ void k_lbvh_write(QueryArgs A, LbvhView T, const int *qoff, uint64_t 
   lbvh_visit(A, T, q, [&](int t) { outb[o++] = ((uint64_t)q << 32) | (uint32_t)t; });
 }
 
-static int lbvh_half(Scene &s, int qtype, int etype, const double *x, const double *p, int *qoff_out_n,
-                     DBuf &qoff_buf, DBuf &out_buf) {
+static int lbvh_half(Scene &s, int qtype, int etype, const double *x, const double *p, double /*cell*/,
+                     int *qoff_out_n, DBuf &qoff_buf, DBuf &out_buf) {
   const int nq = qtype == 0 ? s.nsv : s.nse;
   const int ne = etype == 1 ? s.nst : s.nse;
   const int nbk = blocks_for(ne > 0 ? ne : 1, kHB);
@@ -693,16 +693,36 @@ static int sort_half(Scene &s, int P, int nq, DBuf &keys, DBuf &sorted) {
   return BAL_OK;
 }
 
+// |p_i| per vertex, summed for the pass's mean sweep length
+__global__ void k_sweep_len(const double *__restrict__ p, double *__restrict__ out, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = sqrt(p[3 * i] * p[3 * i] + p[3 * i + 1] * p[3 * i + 1] + p[3 * i + 2] * p[3 * i + 2]);
+}
+
+// Hash cell of a pass.  At rest the cell is the mean surface edge length; a
+// swept pass widens it by twice the mean sweep length: swept boxes cover a
+// few cells instead of dozens (each of which also holds dozens of swept
+// entries), and few entries or queries pass the large-box thresholds.  The
+// candidate set is the box-overlap set whatever the cell.
+static double pass_cell(Scene &s, const double *p) {
+  if (p == nullptr || s.N <= 0 || s.h_plen.grow((size_t)(s.N + 1) * sizeof(double))) return s.cell;
+  hipLaunchKernelGGL(k_sweep_len, dim3(blocks_for(s.N, kHB)), dim3(kHB), 0, s.stream, p, s.h_plen.as<double>(), s.N);
+  const double mean = reduce_sum(s, s.h_plen.as<double>(), s.N) / s.N;
+  return std::isfinite(mean) ? s.cell + 2.0 * mean : s.cell;
+}
+
 int build_candidates(Scene &s, PairList &out, const double *x, const double *p) {
   out.n = 0;
   if (s.nsv == 0 && s.nse == 0) return BAL_OK;
-  auto half = s.desc.broad_phase == BAL_BROAD_LBVH ? lbvh_half : hash_half;
+  const bool lbvh = s.desc.broad_phase == BAL_BROAD_LBVH;
+  auto half = lbvh ? lbvh_half : hash_half;
+  const double cell = lbvh ? s.cell : pass_cell(s, p);
   int nq_pt = 0, nq_ee = 0;
-  const int Ppt = half(s, 0, 1, x, p, &nq_pt, s.qoff_pt, s.out_pt);
+  const int Ppt = half(s, 0, 1, x, p, cell, &nq_pt, s.qoff_pt, s.out_pt);
   if (Ppt < 0) return Ppt;
   int rc = sort_half(s, Ppt, nq_pt, s.out_pt, s.h_sorted_pt);
   if (rc) return rc;
-  const int Pee = half(s, 2, 2, x, p, &nq_ee, s.qoff_ee, s.out_ee);
+  const int Pee = half(s, 2, 2, x, p, cell, &nq_ee, s.qoff_ee, s.out_ee);
   if (Pee < 0) return Pee;
   if ((rc = sort_half(s, Pee, nq_ee, s.out_ee, s.h_sorted_ee))) return rc;
   const int total = Ppt + Pee;
