@@ -25,6 +25,7 @@ two of the cubes (face to face, 0.5 mm apart: inside dhat) and scales it by
 Other modes (one JSON line each):
   --large       one frame of the large chain net (1,762,560 tets) in FP64 and mixed
   --ablations   the stacked boxes with warm_start = 0 and with use_al = 0 (FP64)
+  --ablations-net  the same ablations on the chain net (mixed, its first 2 steps)
   --scale       one step of 60 tumbling blocks (8.9M tets), free and under an
                 active-pair memory limit (the line search's halving, Sec. 5.2)
   --traffic boxes|grid
@@ -372,6 +373,37 @@ def mode_ablations(sc, steps, stream, ccd_rule):
     print(json.dumps(dict(metric=METRIC, workload=sc["name"], ablations=out)), flush=True)
 
 
+def mode_ablations_net(stream, ccd_rule, steps=2):
+    """The two ablations on the chain net as its workload states it (mixed
+    precision, tolerances 1e-4), a bounded sample of its first `steps` steps.
+    Every configuration stops these steps at the 1000-iteration Newton cap,
+    so the comparison is per Newton iteration: PCG and warm-start iterations
+    and seconds per Newton iteration, and the steps' end states."""
+    import scenes
+    from paper_2407_00046_amd import Scene
+    sc = scenes.chain_net()
+    print(f"[bench] {sc['name']}: {sc['tets'].shape[0]} tets, {sc['rest_pos'].shape[0]} vertices", flush=True)
+    out = {}
+    for name, kw in (("bal", {}), ("no_warm_start", dict(warm_start=0)), ("no_al", dict(use_al=0))):
+        g = Scene(sc, precision="mixed", device=0, stream=stream, ccd_rule=ccd_rule, **TOL, **kw)
+        recs = []
+        for _ in range(steps):
+            st = g.step(allow=(0, -7))
+            recs.append({k: st[k] for k in ("status", "newton_iters", "pcg_iters", "warm_iters", "n_active_max",
+                                            "n_aug_max", "sec_total", "sec_pcg", "min_dist")})
+        g.close()
+        nn = sum(r["newton_iters"] for r in recs)
+        out[name] = dict(steps=recs, newton=nn,
+                         pcg_per_newton=sum(r["pcg_iters"] for r in recs) / nn,
+                         warm_per_newton=sum(r["warm_iters"] for r in recs) / nn,
+                         ms_per_newton=1e3 * sum(r["sec_total"] for r in recs) / nn)
+        print(f"[bench] net ablation {name}: {nn} Newton, {out[name]['pcg_per_newton']:.1f} PCG + "
+              f"{out[name]['warm_per_newton']:.1f} warm per Newton iteration, {out[name]['ms_per_newton']:.2f} ms "
+              f"per Newton iteration", flush=True)
+    print(json.dumps(dict(metric=METRIC, workload=sc["name"], precision="mixed", ccd_rule=ccd_rule,
+                          sample=f"first {steps} of the workload's 5 steps", ablations=out)), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -384,6 +416,7 @@ def main():
     ap.add_argument("--broad-phase", default="hash", choices=["hash", "lbvh"])
     ap.add_argument("--large", action="store_true")
     ap.add_argument("--ablations", action="store_true")
+    ap.add_argument("--ablations-net", action="store_true")
     ap.add_argument("--scale", action="store_true")
     ap.add_argument("--traffic", choices=["boxes", "grid"])
     args = ap.parse_args()
@@ -404,6 +437,9 @@ def main():
         return
     if args.scale:
         mode_scale(stream, args.ccd_rule)
+        return
+    if args.ablations_net:
+        mode_ablations_net(stream, args.ccd_rule)
         return
     sc = scenes.stacked_boxes(n_cubes=8, cells=16, seed=0)
     print(f"[bench] workload {sc['name']}: {sc['tets'].shape[0]} tets, {sc['rest_pos'].shape[0]} vertices", flush=True)

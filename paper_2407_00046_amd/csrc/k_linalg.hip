@@ -652,8 +652,8 @@ struct BsrView {
   const int *up;        // transposed rows: pointer
   const int2 *ue;       // (row m, block position) of the blocks (m, j), m > j
   const MT *D;          // diagonal blocks
-  const int *cp, *cc, *cs;  // contact rows: pointer, column of the merged blocks (cs unused)
-  const MT *pblk;
+  const int *cp, *cc;   // contact rows: pointer, column of the merged blocks
+  const MT *pblk;       // merged contact blocks
   const int2 *ent;      // FP32 storage: per row, lower then transposed entries (operand, block)
   int ndummy;           // index of the closing dummy entry
   int npad;             // index of the pad entries closing ci and ue (and of the spare block)
@@ -663,14 +663,14 @@ template <typename MT>
 static BsrView<MT> bsr_view(const Scene &s) {
   return BsrView<MT>{s.row_ptr.as<int>(), s.col_idx.as<int>(), static_cast<const MT *>(s.val.p), s.up_ptr.as<int>(),
                      s.up_ent.as<int2>(), static_cast<const MT *>(s.Dblk.p), s.cm_ptr.as<int>(),
-                     s.cm_col.as<int>(), nullptr, static_cast<const MT *>(s.cm_blk.p),
+                     s.cm_col.as<int>(), static_cast<const MT *>(s.cm_blk.p),
                      s.ent.as<int2>(), 2 * s.nnzb, s.nnzb};
 }
 
 template <typename MT>
 static std::vector<uintptr_t> bsr_sig(const BsrView<MT> &B) {
   return {(uintptr_t)B.rp, (uintptr_t)B.ci, (uintptr_t)B.val, (uintptr_t)B.up, (uintptr_t)B.ue, (uintptr_t)B.D,
-          (uintptr_t)B.cp, (uintptr_t)B.cc, (uintptr_t)B.cs, (uintptr_t)B.pblk, (uintptr_t)B.ent};
+          (uintptr_t)B.cp, (uintptr_t)B.cc, (uintptr_t)B.pblk, (uintptr_t)B.ent};
 }
 
 // Workgroups are handed to the 8 XCDs round-robin; this permutation gives
@@ -883,11 +883,11 @@ __device__ __forceinline__ void blk_sel_t(const MT *a, const VT *w, bool tr, boo
   acc[2] += on ? d2 : (VT)0;
 }
 
-// The row's contact blocks (per-pair block grids read through the row's
-// sorted source list), kC entries per lane per pass: all their indices, then
-// all blocks and operand entries, then the arithmetic, so that a row with
-// many contacts costs a few rounds of memory latency rather than two per
-// entry.  Lanes past the row's end reread a valid entry and drop it.
+// The row's merged contact blocks (one per distinct column, stored in row
+// order), kC entries per lane per pass: all their indices and blocks, then
+// all operand entries, then the arithmetic, so that a row with many
+// contacts costs a few rounds of memory latency rather than two per entry.
+// Lanes past the row's end reread a valid entry and drop it.
 constexpr int kC = 4;
 template <typename MT, typename VT, bool MASK, typename F>
 __device__ __forceinline__ void contact_rows(int c0, int c1, int g, const BsrView<MT> &B, const int *__restrict__ grp,
