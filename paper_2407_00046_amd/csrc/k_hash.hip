@@ -24,7 +24,10 @@ constexpr long kLargeCells = 64;
 constexpr long kQueryCells = 4096;
 constexpr int kOff = 1 << 20;
 constexpr int kQG = 8;  // lanes per query (a power of two dividing the wave)
-constexpr int kQSlots = 8;  // keys a query lane keeps from the counting traversal
+// keys a query lane keeps from the counting traversal: as many as a budget
+// of kQSlotBytes for the pass allows, between 8 and 32
+constexpr int kQSlotsMin = 8, kQSlotsMax = 32;
+constexpr double kQSlotBytes = 256.0 * (1 << 20);
 // Bound on the box tests of one pass (direct tests of large entries and of
 // large queries); beyond it the pass reports BAL_E_CAPACITY and the caller
 // shortens the sweep.
@@ -217,36 +220,37 @@ __device__ void visit_query(const QueryArgs &A, int q, int lane, F emit) {
 
 // One thread per (query, lane); the kQG lanes of a query are consecutive
 // lanes of one wave.  Writes the lane's count and the query's total, and
-// keeps the lane's first kQSlots keys in its own slots.  A lane with more
+// keeps the lane's first ks keys in its own slots.  A lane with more
 // raises the overflow flag (a plain store of 1) and the pass traverses
 // again with k_query_write; otherwise k_query_compact moves the slots into
 // place, so that one traversal serves both count and write.
-__global__ void k_query_count_keep(QueryArgs A, int *lcnt, int *qcnt, uint64_t *slots, int *ovf) {
+__global__ void k_query_count_keep(QueryArgs A, int ks, int *lcnt, int *qcnt, uint64_t *slots, int *ovf) {
   int gid = blockIdx.x * blockDim.x + threadIdx.x;
   int q = gid / kQG, lane = gid % kQG;
   if (q >= A.nq) return;  // whole groups leave together
-  uint64_t *mine = slots + (size_t)gid * kQSlots;
+  uint64_t *mine = slots + (size_t)gid * ks;
   int c = 0;
   visit_query(A, q, lane, [&](int t) {
-    if (c < kQSlots) mine[c] = ((uint64_t)q << 32) | (uint32_t)t;
+    if (c < ks) mine[c] = ((uint64_t)q << 32) | (uint32_t)t;
     ++c;
   });
   lcnt[gid] = c;
-  if (c > kQSlots) *ovf = 1;
+  if (c > ks) *ovf = 1;
 #pragma unroll
   for (int m = kQG / 2; m > 0; m >>= 1) c += __shfl_xor(c, m, kQG);
   if (lane == 0) qcnt[q] = c;
 }
 
-__global__ void k_query_compact(int nq, const int *lcnt, const int *qoff, const uint64_t *slots, uint64_t *outb) {
+__global__ void k_query_compact(int nq, int ks, const int *lcnt, const int *qoff, const uint64_t *slots,
+                                uint64_t *outb) {
   int gid = blockIdx.x * blockDim.x + threadIdx.x;
   int q = gid / kQG, lane = gid % kQG;
   if (q >= nq) return;
   int o = qoff[q];
   const int *lc = lcnt + (size_t)q * kQG;
   for (int k = 0; k < lane; ++k) o += lc[k];
-  const int c = lc[lane];  // <= kQSlots: no lane overflowed
-  const uint64_t *mine = slots + (size_t)gid * kQSlots;
+  const int c = lc[lane];  // <= ks: no lane overflowed
+  const uint64_t *mine = slots + (size_t)gid * ks;
   for (int m = 0; m < c; ++m) outb[o + m] = mine[m];
 }
 
@@ -320,8 +324,14 @@ static int hash_half(Scene &s, int qtype, int etype, const double *x, const doub
       s.h_off.grow((size_t)(ne + 1) * sizeof(int)) || s.h_large.grow((size_t)(ne + 1) * sizeof(int)) ||
       s.h_nlarge.grow(3 * sizeof(int)) || s.hq_lo.grow((size_t)(nq + 1) * sizeof(uint8_t)) ||
       s.h_lcnt.grow(((size_t)nq * kQG + 1) * sizeof(int)) ||
-      s.h_slots.grow(((size_t)nq * kQG * kQSlots + 1) * sizeof(uint64_t)))
+      s.h_slots.grow(((size_t)nq * kQG * kQSlotsMin + 1) * sizeof(uint64_t)))
     return BAL_E_OOM;
+  int ks = (int)std::min<double>(kQSlotsMax, kQSlotBytes / ((double)std::max(nq, 1) * kQG * sizeof(uint64_t)));
+  ks = std::max(ks, kQSlotsMin);
+  if (s.h_slots.grow(((size_t)nq * kQG * ks + 1) * sizeof(uint64_t))) {  // a failed grow frees the buffer
+    ks = kQSlotsMin;
+    if (s.h_slots.grow(((size_t)nq * kQG * ks + 1) * sizeof(uint64_t))) return BAL_E_OOM;
+  }
   Box *ebox = s.hb_lo.as<Box>();
   int *nlarge_d = s.h_nlarge.as<int>();  // [0] large entries, [1] large queries, [2] slot overflow
   hipMemsetAsync(nlarge_d, 0, 3 * sizeof(int), s.stream);
@@ -370,7 +380,7 @@ static int hash_half(Scene &s, int qtype, int etype, const double *x, const doub
   hipMemsetAsync(s.h_qcnt.p, 0, (nq + 1) * sizeof(int), s.stream);
   const int qthreads = nq * kQG;  // nq * kQG < 2^31: nq is a surface count
   if (nq > 0)
-    hipLaunchKernelGGL(k_query_count_keep, dim3(blocks_for(qthreads, kHB)), dim3(kHB), 0, s.stream, A,
+    hipLaunchKernelGGL(k_query_count_keep, dim3(blocks_for(qthreads, kHB)), dim3(kHB), 0, s.stream, A, ks,
                        s.h_lcnt.as<int>(), s.h_qcnt.as<int>(), s.h_slots.as<uint64_t>(), nlarge_d + 2);
   hipMemcpyAsync(hn + 2, nlarge_d + 2, sizeof(int), hipMemcpyDeviceToHost, s.stream);
   int P = scan_exclusive(s, s.h_qcnt.as<int>(), qoff_buf.as<int>(), nq + 1);  // synchronises
@@ -381,7 +391,7 @@ static int hash_half(Scene &s, int qtype, int etype, const double *x, const doub
       hipLaunchKernelGGL(k_query_write, dim3(blocks_for(qthreads, kHB)), dim3(kHB), 0, s.stream, A,
                          s.h_lcnt.as<int>(), qoff_buf.as<int>(), out_buf.as<uint64_t>());
     else
-      hipLaunchKernelGGL(k_query_compact, dim3(blocks_for(qthreads, kHB)), dim3(kHB), 0, s.stream, nq,
+      hipLaunchKernelGGL(k_query_compact, dim3(blocks_for(qthreads, kHB)), dim3(kHB), 0, s.stream, nq, ks,
                          s.h_lcnt.as<int>(), qoff_buf.as<int>(), s.h_slots.as<uint64_t>(), out_buf.as<uint64_t>());
   }
   *qoff_out_n = nq;
