@@ -4,15 +4,18 @@
 // Entry primitives (triangles for point-triangle, edges for edge-edge) are
 // inserted into every grid cell their dhat-inflated box (optionally swept
 // over [x, x + p]) overlaps; cells hash into a bucket table built by a
-// counting sort.  Each query primitive (surface vertex, surface edge) scans
-// the cells of its own box; a pair is reported only in the lowest cell of
-// the overlap of the two cell ranges, so it is found once.  Primitives
-// whose box spans more than kLargeCells cells (big obstacle faces) are kept
-// out of the grid and tested directly.  Each query is served by kQG lanes
-// that split its cells' bucket entries (and its direct tests) between them;
-// queries count first, then write at scanned offsets, and the emit pass sorts
-// each query's segment, so the final list is in canonical (kind, a, b) order
-// with no global sort and no atomics in the output.
+// counting sort.  The cell is the mean surface edge length, widened in a
+// swept pass by twice the mean sweep length.  Each query primitive (surface
+// vertex, surface edge) scans the cells of its own box; a pair is reported
+// only in the lowest cell of the overlap of the two cell ranges, so it is
+// found once.  Primitives whose box spans more than kLargeCells cells (big
+// obstacle faces) are kept out of the grid and tested directly.  Each query
+// is served by kQG lanes that split its cells' bucket entries (and its
+// direct tests) between them; one traversal counts each lane's partners
+// and keeps the first few in the lane's slots, which are compacted at
+// scanned offsets (a second traversal writes them when a lane found more),
+// and one radix sort of the (query, partner) keys per half puts the list in
+// canonical (kind, a, b) order with no atomics in the output.
 #include <hipcub/hipcub.hpp>
 
 #include "bal_internal.h"
