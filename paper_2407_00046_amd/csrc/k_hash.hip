@@ -27,10 +27,7 @@ constexpr long kLargeCells = 64;
 constexpr long kQueryCells = 4096;
 constexpr int kOff = 1 << 20;
 constexpr int kQG = 8;  // lanes per query (a power of two dividing the wave)
-// keys a query lane keeps from the counting traversal: as many as a budget
-// of kQSlotBytes for the pass allows, between 8 and 32
-constexpr int kQSlotsMin = 8, kQSlotsMax = 32;
-constexpr double kQSlotBytes = 256.0 * (1 << 20);
+constexpr int kQSlots = 8;  // keys a query lane keeps from the counting traversal
 // Bound on the box tests of one pass (direct tests of large entries and of
 // large queries); beyond it the pass reports BAL_E_CAPACITY and the caller
 // shortens the sweep.
@@ -327,14 +324,9 @@ static int hash_half(Scene &s, int qtype, int etype, const double *x, const doub
       s.h_off.grow((size_t)(ne + 1) * sizeof(int)) || s.h_large.grow((size_t)(ne + 1) * sizeof(int)) ||
       s.h_nlarge.grow(3 * sizeof(int)) || s.hq_lo.grow((size_t)(nq + 1) * sizeof(uint8_t)) ||
       s.h_lcnt.grow(((size_t)nq * kQG + 1) * sizeof(int)) ||
-      s.h_slots.grow(((size_t)nq * kQG * kQSlotsMin + 1) * sizeof(uint64_t)))
+      s.h_slots.grow(((size_t)nq * kQG * kQSlots + 1) * sizeof(uint64_t)))
     return BAL_E_OOM;
-  int ks = (int)std::min<double>(kQSlotsMax, kQSlotBytes / ((double)std::max(nq, 1) * kQG * sizeof(uint64_t)));
-  ks = std::max(ks, kQSlotsMin);
-  if (s.h_slots.grow(((size_t)nq * kQG * ks + 1) * sizeof(uint64_t))) {  // a failed grow frees the buffer
-    ks = kQSlotsMin;
-    if (s.h_slots.grow(((size_t)nq * kQG * ks + 1) * sizeof(uint64_t))) return BAL_E_OOM;
-  }
+  const int ks = kQSlots;
   Box *ebox = s.hb_lo.as<Box>();
   int *nlarge_d = s.h_nlarge.as<int>();  // [0] large entries, [1] large queries, [2] slot overflow
   hipMemsetAsync(nlarge_d, 0, 3 * sizeof(int), s.stream);
