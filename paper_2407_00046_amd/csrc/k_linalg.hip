@@ -793,9 +793,11 @@ __device__ __forceinline__ void row_fetch(int i, int t, int l0, int nl, int u0, 
 // lanes past the row's end read the dummy entry and drop their product by a
 // select, so the compiler keeps every batch's loads in flight together
 // (measured: the 128^3-grid product 246 -> 238 us, a PCG iteration on the
-// stacked boxes 15.8 -> 15.3 us).  FP64 storage keeps the predicated walk of
-// the lower and transposed lists, whose 4-byte lower-entry index matters
-// more there than the branches (the single list made it 392 -> 403 us).
+// stacked boxes 15.8 -> 15.3 us).  The plain and warm-start products with
+// FP64 storage keep the predicated walk of the lower and transposed lists,
+// whose 4-byte lower-entry index matters more there than the branches (the
+// single list made the grid product 392 -> 403 us); the FP64 PCG product
+// walks the two lists without branches (row_fetch_split).
 template <typename MT>
 constexpr bool kUnifiedWalk = sizeof(MT) == 4;
 
@@ -1255,11 +1257,11 @@ __device__ void block_sums(const double *const *src, const int *n, double *out) 
 // stopping rules (App. B: relative residual, stagnation over the window, cap;
 // p.q <= 0 is a breakdown); block 0 stores it in slot k & 1.  Then
 // p_k = z + beta_k p_{k-1} (the row owner stores it), q = A p_k and the
-// partial p_k.q.  The partial loads are issued first, then the row's
-// indices, blocks and the raw z and p_{k-1} entries of its first pass; beta
-// is formed while these are in flight.  p is double-buffered (p_new never
-// aliases p_old) and so is the p.q partial array (this launch reads one and
-// writes the other).
+// partial p_k.q.  The row's extents are loaded with the control block, then
+// the previous partials, then the first pass's indices, blocks and raw z and
+// p_{k-1} entries; beta is formed while these are in flight.  p is
+// double-buffered (p_new never aliases p_old) and so is the p.q partial
+// array (this launch reads one and writes the other).
 template <typename MT, typename VT>
 __global__ __launch_bounds__(kBS) void k_cg_dir_spmv(int N, int k, BsrView<MT> B, const VT *__restrict__ z,
                                                      const VT *__restrict__ p_old, VT *__restrict__ p_new,
@@ -1268,11 +1270,11 @@ __global__ __launch_bounds__(kBS) void k_cg_dir_spmv(int N, int k, BsrView<MT> B
   const int tile = xcd_tile();
   const long t = (long)tile * blockDim.x + threadIdx.x;
   const int i = t / kG < N ? (int)(t / kG) : -1, g = (int)(t % kG);
-  // the row's extents depend on nothing in the control block: their loads
-  // are issued with the control block's, all before the first wait (one
-  // exit test over every control word, so that no load waits for another)
-  // (lanes past the last row read row 0's and ignore them: no branch, so
-  // no copy of a loaded register that would wait for it)
+  // The row's extents depend on nothing in the control block, so their
+  // loads are issued with the control block's, before the first wait.  One
+  // exit test covers every control word, so no load waits for another.
+  // Lanes past the last row read row 0's extents and ignore them: with no
+  // branch there is no copy of a loaded register that would wait for it.
   const int ir = i >= 0 ? i : 0;
   const int rp0 = B.rp[ir], rp1 = B.rp[ir + 1], up0 = B.up[ir], up1 = B.up[ir + 1];
   const int c0 = i >= 0 ? B.cp[ir] : 0, c1 = i >= 0 ? B.cp[ir + 1] : 0;

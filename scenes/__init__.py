@@ -393,7 +393,7 @@ def tumbling_blocks(n_x=3, n_z=4, n_layers=5, cells=31, cell=0.01, gap=0.005, se
     rotated blocks of cells^3 cells x 5 tets stacked in columns (each block
     `gap` above the highest point of the one below, the lowest layer `gap`
     above the floor) inside an open box.  The default, 60 blocks of 31^3
-    cells (8,936,700 tets, 1,966,080 vertices), stands in for the paper's
+    cells (8,937,300 tets, 1,966,080 vertices), stands in for the paper's
     tumbling-T-rex scene (its Table of scenarios: 9M tets, E = 5e5, one step
     of h = 1/30)."""
     rng = np.random.default_rng(seed)
