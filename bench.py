@@ -26,6 +26,7 @@ Other modes (one JSON line each):
   --large       one frame of the large chain net (1,762,560 tets) in FP64 and mixed
   --ablations   the stacked boxes with warm_start = 0 and with use_al = 0 (FP64)
   --ablations-net  the same ablations on the chain net (mixed, its first 2 steps)
+  --friction CHI   the stacked boxes' FP64 steps with friction coefficient CHI
   --scale       one step of 60 tumbling blocks (8.9M tets), free and under an
                 active-pair memory limit (the line search's halving, Sec. 5.2)
   --traffic boxes|grid
@@ -373,6 +374,17 @@ def mode_ablations(sc, steps, stream, ccd_rule):
     print(json.dumps(dict(metric=METRIC, workload=sc["name"], ablations=out)), flush=True)
 
 
+def mode_friction(sc, chi, steps, stream, ccd_rule):
+    """The stacked boxes' FP64 steps with fully-implicit friction (Sec. 4.1,
+    coefficient chi, eps_v = dhat): the workload runs frictionless as
+    configured; this measures what the friction terms cost."""
+    r, _ = run_fp64(sc, steps, 0, stream, ccd_rule=ccd_rule, friction=chi)
+    print(f"[bench] friction {chi}: {r['s_per_step']:.3f} s/step, {r['newton_iters_per_step']:.1f} Newton, "
+          f"{r['pcg_iters_per_step']:.0f} PCG per step, {r['converged_steps']} of {r['steps']} steps converged",
+          flush=True)
+    print(json.dumps(dict(metric=METRIC, workload=sc["name"], friction=chi, fp64=r)), flush=True)
+
+
 def mode_ablations_net(stream, ccd_rule, steps=2):
     """The two ablations on the chain net as its workload states it (mixed
     precision, tolerances 1e-4), a bounded sample of its first `steps` steps.
@@ -417,6 +429,8 @@ def main():
     ap.add_argument("--large", action="store_true")
     ap.add_argument("--ablations", action="store_true")
     ap.add_argument("--ablations-net", action="store_true")
+    ap.add_argument("--friction", type=float, default=0.0,
+                    help="run the stacked boxes' FP64 steps with this friction coefficient (a measurement mode)")
     ap.add_argument("--scale", action="store_true")
     ap.add_argument("--traffic", choices=["boxes", "grid"])
     args = ap.parse_args()
@@ -445,6 +459,9 @@ def main():
     print(f"[bench] workload {sc['name']}: {sc['tets'].shape[0]} tets, {sc['rest_pos'].shape[0]} vertices", flush=True)
     if args.ablations:
         mode_ablations(sc, args.steps, stream, args.ccd_rule)
+        return
+    if args.friction > 0.0:
+        mode_friction(sc, args.friction, args.steps, stream, args.ccd_rule)
         return
     fp64, states = run_fp64(sc, args.steps, args.warmup, stream, ccd_rule=args.ccd_rule, broad_phase=args.broad_phase)
     print(f"[bench] fp64: {fp64['s_per_step']:.3f} s/step", flush=True)
