@@ -306,25 +306,43 @@ static int linearize_at(Scene &s, const double *x, int project, double sigma) {
 
 // L_sigma at xp over candidate pairs pl (barrier) and A' (augmentation);
 // returns BAL_OK with *L, or sets *valid = 0 if some J <= 0 or d <= 0.
+// The part sums, the active count and the flags are left on the device and
+// read back together: one synchronisation per evaluation.
 static int energy_at(Scene &s, const double *xp, PairList &pl, double sigma, double *L, int *valid, int *nact) {
   hipMemsetAsync(s.flags.p, 0, sizeof(int), s.stream);
   launch_elements(s, xp, EM_ENERGY, 0);
   launch_inertia_energy(s, xp, s.node_e.as<double>());
-  if (s.cand_e.grow((size_t)(pl.n + 1) * 8)) return BAL_E_OOM;
+  if (s.cand_e.grow((size_t)(pl.n + 1) * 8) || s.red_slots.grow(8 * sizeof(double))) return BAL_E_OOM;
   launch_pair_barrier_energy(s, pl, xp, sigma, s.cand_e.as<double>(), s.flags.as<int>());
   launch_aug_energy(s, xp, sigma, s.aug_e.as<double>(), s.aug_d.as<double>(), s.flags.as<int>());
-  double e = reduce_sum(s, s.tet_e.as<double>(), s.T) + reduce_sum(s, s.node_e.as<double>(), s.N);
-  e += reduce_sum(s, s.cand_e.as<double>(), pl.n);
-  if (s.n_aug) e += reduce_sum(s, s.aug_e.as<double>(), s.n_aug);
+  // slots: elements, inertia, barrier, augmentation, friction, active count, flags
+  double *sl = s.red_slots.as<double>();
+  hipMemsetAsync(sl, 0, 8 * sizeof(double), s.stream);
+  reduce_sum_to(s, s.tet_e.as<double>(), s.T, sl);
+  reduce_sum_to(s, s.node_e.as<double>(), s.N, sl + 1);
+  reduce_sum_to(s, s.cand_e.as<double>(), pl.n, sl + 2);
+  if (s.n_aug) reduce_sum_to(s, s.aug_e.as<double>(), s.n_aug, sl + 3);
   // friction potential with the frames of the last linearization (Sec. 4.1)
-  if (s.desc.friction > 0.0 && s.uni.n > 0) {
+  const bool fric = s.desc.friction > 0.0 && s.uni.n > 0;
+  if (fric) {
     launch_friction_energy(s, xp, s.fr_e.as<double>());
-    e += reduce_sum(s, s.fr_e.as<double>(), s.uni.n);
+    reduce_sum_to(s, s.fr_e.as<double>(), s.uni.n, sl + 4);
   }
-  int f = read_flags_and_clear(s);
+  count_less_to(s, pl.d.as<double>(), pl.n, s.desc.dhat, sl + 5);
+  hipMemcpyAsync(sl + 6, s.flags.p, sizeof(int), hipMemcpyDeviceToDevice, s.stream);
+  double *h = reinterpret_cast<double *>(static_cast<char *>(s.pin.p) + kPinEnergy);
+  hipMemcpyAsync(h, sl, 7 * sizeof(double), hipMemcpyDeviceToHost, s.stream);
+  if (hipStreamSynchronize(s.stream) != hipSuccess) return BAL_E_HIP;
+  hipMemsetAsync(s.flags.p, 0, sizeof(int), s.stream);
+  int f;
+  std::memcpy(&f, h + 6, sizeof(int));
+  double e = h[0] + h[1];
+  e += h[2];
+  if (s.n_aug) e += h[3];
+  if (fric) e += h[4];
   *valid = f == 0;
   *L = e;
-  *nact = reduce_count_less(s, pl.d.as<double>(), pl.n, s.desc.dhat);
+  *nact = (int)llround(h[5]);
   return BAL_OK;
 }
 
@@ -358,6 +376,24 @@ static double min_or(Scene &s, PairList &pl, double fallback) {
   if (pl.n == 0) return fallback;
   double m = reduce_min(s, pl.d.as<double>(), pl.n);
   return m;
+}
+
+// min d over a pair list and the count of pairs inside dhat, read back
+// together (INFINITY and 0 for an empty list)
+static int min_and_count(Scene &s, PairList &pl, double dh, double *min_d, int *count) {
+  *min_d = INFINITY;
+  *count = 0;
+  if (pl.n == 0) return BAL_OK;
+  if (s.red_slots.grow(8 * sizeof(double))) return BAL_E_OOM;
+  double *sl = s.red_slots.as<double>();
+  reduce_min_to(s, pl.d.as<double>(), pl.n, sl);
+  count_less_to(s, pl.d.as<double>(), pl.n, dh, sl + 1);
+  double *h = reinterpret_cast<double *>(static_cast<char *>(s.pin.p) + kPinEnergy);
+  hipMemcpyAsync(h, sl, 2 * sizeof(double), hipMemcpyDeviceToHost, s.stream);
+  if (hipStreamSynchronize(s.stream) != hipSuccess) return BAL_E_HIP;
+  *min_d = h[0];
+  *count = (int)llround(h[1]);
+  return BAL_OK;
 }
 
 static void copy3(Scene &s, double *dst, const double *src) {
@@ -394,8 +430,9 @@ static int newton_solve(Scene &s, bal_step_stats *st, bool record) {
   for (int l = 0; l < d.max_newton; ++l) {
     tc = clk::now();
     launch_pair_distance(s, s.cand, x, s.cand.d.as<double>(), s.cand.cs.as<int>());
-    double min_d = min_or(s, s.cand, INFINITY);
-    int n_active = reduce_count_less(s, s.cand.d.as<double>(), s.cand.n, dh);
+    double min_d = INFINITY;
+    int n_active = 0;
+    if ((rc = min_and_count(s, s.cand, dh, &min_d, &n_active))) return rc;
     S.sec_collision += since(tc);
     if (d.use_al) {
       if (min_d > 1e-2 * dh) {
@@ -1109,7 +1146,7 @@ void bal_destroy_scene(bal_scene *h) {
                   &s.h_cnt, &s.h_off, &s.h_key, &s.h_prim, &s.h_bcnt, &s.h_bstart, &s.h_bfill, &s.h_skey,
                   &s.h_sprim, &s.h_large, &s.h_nlarge, &s.h_qcnt, &s.h_lcnt, &s.h_slots, &s.h_plen, &s.h_qoff, &s.h_out, &s.qoff_pt, &s.out_pt,
                   &s.qoff_ee, &s.out_ee, &s.lb_part, &s.lb_key, &s.lb_key2, &s.lb_tmp, &s.lb_prim, &s.lb_child,
-                  &s.lb_parent, &s.lb_lparent, &s.lb_arrive, &s.lb_ibox, &s.h_sorted_pt, &s.h_sorted_ee, &s.r, &s.z, &s.pv, &s.pv2, &s.q, &s.pcg_ctl, &s.warm_ctl, &s.partial, &s.counter,
+                  &s.lb_parent, &s.lb_lparent, &s.lb_arrive, &s.lb_ibox, &s.h_sorted_pt, &s.h_sorted_ee, &s.r, &s.z, &s.pv, &s.pv2, &s.q, &s.pcg_ctl, &s.warm_ctl, &s.partial, &s.red_slots, &s.counter,
                   &s.scan_tmp, &s.red_out, &s.flags, &s.node_e, &s.cand_e, &s.mask, &s.mask_off, &s.tau, &s.rhs, &s.psweep};
   for (DBuf *b : bufs) b->release();
   PairList *pls[] = {&s.cand, &s.cand2, &s.uni, &s.augtmp};

@@ -21,6 +21,9 @@ struct DBuf {
   template <typename T> T *as() const { return static_cast<T *>(p); }
 };
 
+// byte offset of the energy evaluation's readback slots in the pinned scratch
+constexpr size_t kPinEnergy = 16384;
+
 // Stiffness-group bins of the warm start: group label + 32 clamped to [0, 63].
 constexpr int kGroups = 64;
 constexpr int kGroupOffset = 32;
@@ -86,9 +89,11 @@ struct Scene {
   DBuf h_sorted_pt, h_sorted_ee;  // candidate keys of each half in canonical order
   // PCG
   DBuf ent;  // FP32 storage: per row its lower then transposed entries (operand, block), one dummy at the end
-  DBuf r, z, pv, pv2, q, pcg_ctl, warm_ctl, partial, counter, scan_tmp, red_out, flags;
+  DBuf r, z, pv, pv2, q, pcg_ctl, warm_ctl, partial, counter, scan_tmp, red_out, red_slots, flags;
   DBuf node_e, cand_e, mask, mask_off, tau, rhs, psweep;
-  DBuf pin;     // pinned host scratch (hipHostMalloc)
+  DBuf pin;     // pinned host scratch (hipHostMalloc, 64 KiB): bytes 0-4095 scalar and
+                // control-block readbacks, 4096- candidate-pass counts, kPinEnergy- the
+                // energy readback, 32768- the pipelined PCG chunks' control-block copies
   // graph replay of PCG chunks (re-captured when a buffer moves)
   bool use_graphs = true;
   bool own_stream = false;
@@ -130,6 +135,9 @@ int scan_exclusive_async(Scene &s, const int *in, int *out, int n);  // 0, or -1
 double reduce_sum(Scene &s, const double *in, int n);
 double reduce_min(Scene &s, const double *in, int n);
 int reduce_count_less(Scene &s, const double *in, int n, double thr);
+void reduce_sum_to(Scene &s, const double *in, int n, double *dst);
+void reduce_min_to(Scene &s, const double *in, int n, double *dst);
+void count_less_to(Scene &s, const double *in, int n, double thr, double *dst);
 void launch_predictor(Scene &s);
 void launch_axpy_state(Scene &s, double *out, const double *a, const double *b, double alpha, int n3);
 void launch_inertia_energy(Scene &s, const double *x, double *out_per_node);

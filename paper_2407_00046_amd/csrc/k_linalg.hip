@@ -81,6 +81,31 @@ static double reduce_op(Scene &s, const double *in, int n, Op op, double ident) 
 }
 
 double reduce_sum(Scene &s, const double *in, int n) { return reduce_op(s, in, n, OpSum(), 0.0); }
+
+// The same sums and counts left on the device in *dst (stream-ordered, no
+// synchronisation), so that a caller can read several at once: the partial
+// area is reused, which the stream order makes safe.  n <= 0 writes nothing.
+template <typename Op>
+static void reduce_op_to(Scene &s, const double *in, int n, Op op, double ident, double *dst) {
+  if (n <= 0) return;
+  int nb = blocks_for(n, kBS);
+  if (nb > 1024) nb = 1024;
+  double *part = s.red_out.as<double>() + 1;
+  hipLaunchKernelGGL(k_reduce_stage<Op>, dim3(nb), dim3(kBS), 0, s.stream, in, (long)n, part, op, ident);
+  hipLaunchKernelGGL(k_reduce_stage<Op>, dim3(1), dim3(kBS), 0, s.stream, part, (long)nb, dst, op, ident);
+}
+void reduce_sum_to(Scene &s, const double *in, int n, double *dst) { reduce_op_to(s, in, n, OpSum(), 0.0, dst); }
+void reduce_min_to(Scene &s, const double *in, int n, double *dst) {
+  reduce_op_to(s, in, n, OpMin(), INFINITY, dst);
+}
+void count_less_to(Scene &s, const double *in, int n, double thr, double *dst) {
+  if (n <= 0) return;
+  int nb = blocks_for(n, kBS);
+  if (nb > 1024) nb = 1024;
+  double *part = s.red_out.as<double>() + 1;
+  hipLaunchKernelGGL(k_count_less, dim3(nb), dim3(kBS), 0, s.stream, in, (long)n, thr, part);
+  hipLaunchKernelGGL(k_reduce_stage<OpSum>, dim3(1), dim3(kBS), 0, s.stream, part, (long)nb, dst, OpSum(), 0.0);
+}
 double reduce_min(Scene &s, const double *in, int n) { return reduce_op(s, in, n, OpMin(), INFINITY); }
 int reduce_count_less(Scene &s, const double *in, int n, double thr) {
   if (n <= 0) return 0;
