@@ -37,8 +37,12 @@ def test_status_strings():
 
 
 def test_ctypes_layout_matches_c():
+    """Every field of the three ABI structures sits at the C offset, and the
+    sizes agree."""
     import ctypes
     from paper_2407_00046_amd import bal
+    fields = "\n".join(f"  P({T}, {f[0]});" for T in ("bal_scene_desc", "bal_step_stats", "bal_al_state")
+                       for f in getattr(bal, T)._fields_)
     probe = r"""
 #include <stdio.h>
 #include <stddef.h>
@@ -48,9 +52,7 @@ int main(void) {
   printf("bal_scene_desc %zu\n", sizeof(bal_scene_desc));
   printf("bal_step_stats %zu\n", sizeof(bal_step_stats));
   printf("bal_al_state %zu\n", sizeof(bal_al_state));
-  P(bal_scene_desc, n_obs_verts); P(bal_scene_desc, dt); P(bal_scene_desc, gravity); P(bal_scene_desc, dhat);
-  P(bal_scene_desc, max_newton); P(bal_scene_desc, use_al); P(bal_scene_desc, stream);
-  P(bal_step_stats, sigma); P(bal_step_stats, spmv_bytes); P(bal_al_state, aug_kind); P(bal_al_state, s);
+""" + fields + r"""
   return 0;
 }
 """
